@@ -1,0 +1,265 @@
+"""Synthetic workloads: the droplet-on-cylinder family and its test cases.
+
+Every builder returns a :class:`Problem`.  Lengths follow the paper's droplet
+on a circular cylinder (Sec. 3.2, Fig. 6), scaled to the sizes used here; the
+numbers below are inputs of the recipe, not results of the method:
+
+* ``TC_CS`` is the critical temperature of the Carnahan-Starling equation of
+  state for a = 1, b = 4, R = 1 (T_c scales as a / (b R)).
+* ``CS_INIT`` lists the liquid and vapour densities used to initialise
+  droplets; they are the coexistence densities of the plain pseudopotential
+  model at those temperatures, rounded to six digits.
+* The virtual wall density defaults to the mean of the two, which gives a
+  contact angle near 90 degrees.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import geometry as geo
+from .problem import LINK_DTYPE, Problem
+from .rng import Stream
+
+TC_CS = 0.0943287  # a = 1, b = 4, R = 1
+CS_INIT = {0.80: (0.303360, 0.008119), 0.86: (0.269941, 0.024515),
+           0.90: (0.245281, 0.038898)}
+EXP_INIT = (2.783, 0.3675)  # psi = exp(-1/rho), G = -10/3 (Sec. 3.2)
+
+
+def cs_params(t_over_tc: float, a: float = 1.0, b: float = 4.0, R: float = 1.0):
+    return (a, b, R, t_over_tc * TC_CS * a * 4.0 / (b * R))
+
+
+def cs_init_densities(t_over_tc: float):
+    """Initial liquid/vapour densities, interpolated in the table above."""
+    ks = sorted(CS_INIT)
+    t = min(max(t_over_tc, ks[0]), ks[-1])
+    for lo, hi in zip(ks[:-1], ks[1:]):
+        if lo <= t <= hi:
+            w = (t - lo) / (hi - lo)
+            return tuple((1 - w) * CS_INIT[lo][i] + w * CS_INIT[hi][i]
+                         for i in range(2))
+    return CS_INIT[ks[-1]]
+
+
+def mrt_rates(tau: float):
+    """Rates in the order rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy.
+
+    s_nu = 1/tau on the stress moments; s_e = s_eps = s_nu; s_q from the
+    'magic' combination (1/s_nu - 1/2)(1/s_q - 1/2) = 3/16; conserved
+    moments at 1 (their rate does not enter with this forcing)."""
+    snu = 1.0 / tau
+    sq = 8.0 * (2.0 - snu) / (8.0 - snu)
+    return (1.0, snu, snu, 1.0, sq, 1.0, sq, snu, snu)
+
+
+def _problem(nx, ny, shapes, rho0, rho_wall, **kw):
+    solid, owner, links = geo.build(nx, ny, shapes)
+    rw = np.full((ny, nx), float(rho_wall)) if np.isscalar(rho_wall) else rho_wall
+    rho0 = np.where(solid.astype(bool), rw if np.ndim(rw) else rho_wall, rho0)
+    p = Problem(nx=nx, ny=ny, solid=solid, links=links, rho0=rho0,
+                rho_wall=rw, **kw)
+    p.meta["owner"] = owner
+    return p
+
+
+def droplet_on_cylinder(side_x=128, side_y=128, scale=1.0, floor=4, rc=20.0,
+                        centre=(64.0, 40.0), rd=25.0, width=4.0,
+                        t_over_tc=0.86, collision="bgk", tau=1.0,
+                        rule="mls", fix="A", rho_wall=None, name="cfg1"):
+    """Droplet resting on a cylinder above a flat floor; periodic in x and y.
+
+    The floor occupies rows [0, floor) and, through the y wrap, is also the
+    ceiling; its wall sits half-way between rows (q = 1/2).  The droplet is
+    centred on the cylinder's top point."""
+    nx, ny = int(side_x * scale), int(side_y * scale)
+    cx, cy = centre[0] * scale, centre[1] * scale
+    rc, rd = rc * scale, rd * scale
+    rho_l, rho_v = cs_init_densities(t_over_tc)
+    shapes = [geo.Circle(cx, cy, rc)]
+    if floor:
+        shapes.append(geo.Band(0, int(floor * scale)))
+    rho0 = geo.tanh_disc(nx, ny, cx, cy + rc, rd, rho_l, rho_v, width)
+    rw = 0.5 * (rho_l + rho_v) if rho_wall is None else rho_wall
+    p = _problem(nx, ny, shapes, rho0, rw, eos="cs",
+                 eos_params=cs_params(t_over_tc), G=-1.0, collision=collision,
+                 tau=tau, mrt_s=mrt_rates(tau), rule=rule, fix=fix, name=name)
+    p.meta.update(rho_l=rho_l, rho_v=rho_v, rc=rc, rd=rd, cx=cx, cy=cy)
+    return p
+
+
+CFG1_RHO_WALL = 0.05
+
+
+def cfg1(rule="mls", fix="A"):
+    """128x128, floor 4 rows, cylinder R=20 at (64,40), droplet R=25, CS at
+    0.86 Tc, BGK tau = 1, virtual wall density 0.05 (a non-wetting wall on
+    which the original rules survive 1000 steps while they leak mass)."""
+    return droplet_on_cylinder(rule=rule, fix=fix, rho_wall=CFG1_RHO_WALL,
+                               name="cfg1")
+
+
+def cfg2a(rule="mls", fix="B", scale=16.0):
+    """The cfg1 droplet scaled by 16 to 2048x2048 (interface width kept at
+    4), MRT with s_nu = 1/tau, tau = 0.8."""
+    return droplet_on_cylinder(scale=scale, collision="mrt", tau=0.8,
+                               rule=rule, fix=fix, rho_wall=CFG1_RHO_WALL,
+                               name=f"droplet{int(128*scale)}")
+
+
+def couette(r1: float, rule="mls", fix="A", tau=0.8, U=0.01):
+    """Circular Couette flow: inner cylinder radius r1 turning with surface
+    speed U, fixed outer wall at r2 = 2 r1, single phase, rho = 1."""
+    r2 = 2.0 * r1
+    side = int(2 * r2 + 8)
+    c = (side - 1) / 2.0
+    shapes = [geo.Circle(c, c, r1, omega=U / r1), geo.OuterCircle(c, c, r2)]
+    rho0 = np.ones((side, side))
+    p = _problem(side, side, shapes, rho0, 1.0, eos="none", tau=tau,
+                 rule=rule, fix=fix, name=f"couette_r{r1:g}")
+    p.meta.update(r1=r1, r2=r2, c=c, U=U)
+    return p
+
+
+def static_gravity(q: float, rule="mls", fix="none", nx=100, ny=50, g=0.001,
+                   tau=1.0):
+    """Fluid at rest under gravity between two flat walls with fraction q.
+
+    One solid row (y = 0) is the floor and, through the y wrap, the
+    ceiling."""
+    shapes = [geo.Band(0, 1, q_top=q, q_bottom=q)]
+    p = _problem(nx, ny, shapes, np.ones((ny, nx)), 1.0, eos="none", tau=tau,
+                 gravity=(0.0, -g), rule=rule, fix=fix, name=f"gravity_q{q:g}")
+    return p
+
+
+def shear_wave(n: int, U=1e-3, tau=0.8, collision="bgk", mrt_s=None, nx=4):
+    """u_x = U sin(2 pi y / n), rho = 1, no walls, no interaction."""
+    y = np.arange(n, dtype=np.float64)
+    ux0 = np.repeat((U * np.sin(2 * np.pi * y / n))[:, None], nx, axis=1)
+    p = Problem(nx=nx, ny=n, solid=np.zeros((n, nx), np.uint8),
+                links=np.zeros(0, dtype=LINK_DTYPE),
+                rho0=np.ones((n, nx)), rho_wall=np.ones((n, nx)), eos="none",
+                collision=collision, tau=tau,
+                mrt_s=mrt_s if mrt_s is not None else mrt_rates(tau),
+                ux0=ux0, uy0=np.zeros((n, nx)), name=f"shear{n}")
+    return p
+
+
+def flat_interface(eos="cs", t_over_tc=0.86, ny=200, nx=4, tau=1.0,
+                   width=4.0, collision="bgk"):
+    """A liquid slab across a periodic channel with two flat interfaces."""
+    if eos == "cs":
+        rho_l, rho_v = cs_init_densities(t_over_tc)
+        params, G = cs_params(t_over_tc), -1.0
+    else:
+        rho_l, rho_v = EXP_INIT
+        params, G = (1.0, 1.0, 0.0, 0.0), -10.0 / 3.0
+    rho0 = geo.tanh_slab(nx, ny, ny / 4.0, 3.0 * ny / 4.0, rho_l, rho_v, width)
+    return Problem(nx=nx, ny=ny, solid=np.zeros((ny, nx), np.uint8),
+                   links=np.zeros(0, dtype=LINK_DTYPE),
+                   rho0=rho0, rho_wall=np.ones((ny, nx)), eos=eos,
+                   eos_params=params, G=G, collision=collision, tau=tau,
+                   mrt_s=mrt_rates(tau), name=f"slab_{eos}")
+
+
+def free_droplet(n: int, R: float, eos="cs", t_over_tc=0.86, tau=1.0,
+                 width=4.0):
+    """A droplet of radius R in a periodic n x n box, no walls."""
+    if eos == "cs":
+        rho_l, rho_v = cs_init_densities(t_over_tc)
+        params, G = cs_params(t_over_tc), -1.0
+    else:
+        rho_l, rho_v = EXP_INIT
+        params, G = (1.0, 1.0, 0.0, 0.0), -10.0 / 3.0
+    c = (n - 1) / 2.0
+    rho0 = geo.tanh_disc(n, n, c, c, R, rho_l, rho_v, width)
+    return Problem(nx=n, ny=n, solid=np.zeros((n, n), np.uint8),
+                   links=np.zeros(0, dtype=LINK_DTYPE),
+                   rho0=rho0, rho_wall=np.ones((n, n)), eos=eos,
+                   eos_params=params, G=G, tau=tau, mrt_s=mrt_rates(tau),
+                   name=f"drop{n}_R{R:g}")
+
+
+def theta_to_rho_wall(theta_deg: float, rho_l: float, rho_v: float) -> float:
+    """Linear proxy: 30 degrees -> rho_l, 150 degrees -> rho_v."""
+    w = (theta_deg - 30.0) / 120.0
+    return (1.0 - w) * rho_l + w * rho_v
+
+
+def many_cylinders(nx=8192, ny=4096, n=96, rmin=24.0, rmax=96.0, seed=3,
+                   clearance=8.0, t_over_tc=0.86, tau=0.8, rule="mls",
+                   fix="B", width=4.0, max_tries=200000):
+    """n non-overlapping cylinders, each with a droplet on its top point and
+    its own wettability; placement by rejection from a seeded stream."""
+    rs = Stream(seed, 0)
+    rho_l, rho_v = cs_init_densities(t_over_tc)
+    placed = []  # (cx, cy, R, Rd, theta)
+    tries = 0
+    while len(placed) < n:
+        tries += 1
+        assert tries < max_tries, "could not place all cylinders"
+        R = rs.uniform(rmin, rmax)
+        Rd = rs.uniform(1.2, 1.6) * R
+        theta = rs.uniform(30.0, 150.0)
+        bound = R + Rd
+        cx = rs.uniform(R + 2.0, nx - R - 3.0)
+        cy = rs.uniform(R + 2.0, ny - R - 3.0)
+        ok = True
+        for (px, py, pR, pRd, _) in placed:
+            dx = abs(cx - px)
+            dy = abs(cy - py)
+            dx, dy = min(dx, nx - dx), min(dy, ny - dy)
+            if math.hypot(dx, dy) < bound + pR + pRd + clearance:
+                ok = False
+                break
+        if ok:
+            placed.append((cx, cy, R, Rd, theta))
+    shapes = [geo.Circle(cx, cy, R) for (cx, cy, R, _, _) in placed]
+    solid, owner, links = geo.build(nx, ny, shapes)
+    rho0 = np.full((ny, nx), rho_v)
+    Y, X = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    for (cx, cy, R, Rd, _) in placed:
+        dx = X - cx
+        dy = Y - (cy + R)
+        dx -= nx * np.round(dx / nx)
+        dy -= ny * np.round(dy / ny)
+        r = np.sqrt(dx * dx + dy * dy)
+        prof = 0.5 * (rho_l + rho_v) + 0.5 * (rho_l - rho_v) * np.tanh(
+            2.0 * (Rd - r) / width)
+        rho0 = np.maximum(rho0, prof)
+    rw = np.full((ny, nx), 0.5 * (rho_l + rho_v))
+    for k, (_, _, _, _, th) in enumerate(placed):
+        rw[owner == k] = theta_to_rho_wall(th, rho_l, rho_v)
+    rho0 = np.where(solid.astype(bool), rw, rho0)
+    p = Problem(nx=nx, ny=ny, solid=solid, links=links, rho0=rho0,
+                rho_wall=rw, eos="cs", eos_params=cs_params(t_over_tc),
+                G=-1.0, tau=tau, mrt_s=mrt_rates(tau), rule=rule, fix=fix,
+                name=f"cylinders{n}_{nx}x{ny}")
+    p.meta.update(placed=placed, owner=owner)
+    return p
+
+
+def batch_instance(k: int, seed: int = 4, side_lo=64, side_hi=768,
+                   rule="mls", fix="B", width=4.0):
+    """Instance k of the batched droplet-on-cylinder mix (stream
+    seed * 2^32 + k): side, cylinder and droplet radii, T/Tc and tau drawn
+    uniformly; doubly periodic, no floor; the cylinder sits so that
+    cylinder and droplet are centred vertically."""
+    rs = Stream(seed, (seed << 32) + k)
+    side = rs.integers(side_lo, side_hi)
+    rc = rs.uniform(0.10, 0.25) * side
+    rd = rs.uniform(1.1, 1.8) * rc
+    t = rs.uniform(0.80, 0.90)
+    tau = rs.uniform(0.6, 1.2)
+    cx, cy = side / 2.0, side / 2.0 - rd / 2.0
+    rho_l, rho_v = cs_init_densities(t)
+    shapes = [geo.Circle(cx, cy, rc)]
+    rho0 = geo.tanh_disc(side, side, cx, cy + rc, rd, rho_l, rho_v, width)
+    p = _problem(side, side, shapes, rho0, 0.5 * (rho_l + rho_v), eos="cs",
+                 eos_params=cs_params(t), G=-1.0, tau=tau, mrt_s=mrt_rates(tau),
+                 rule=rule, fix=fix, name=f"inst{k}")
+    p.meta.update(side=side, rc=rc, rd=rd, t_over_tc=t)
+    return p
