@@ -1,0 +1,198 @@
+/*
+ * lbm2p: two-phase D2Q9 lattice-Boltzmann time step with curved walls and
+ * mass-conservative boundary corrections, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yu, Li & Wen, "Modified curved boundary scheme for two-phase
+ * lattice Boltzmann simulations" (arXiv:1908.09235).  One time step is
+ *   - the pseudopotential psi(rho) from an equation of state and the
+ *     interaction force of Eq. (16), plus an optional body force rho*g;
+ *   - collision, Eq. (2), with the equilibrium of Eq. (4) and the forcing
+ *     term of Guo et al. that Sec. 3.2 cites (BGK, or a D2Q9
+ *     multiple-relaxation-time form of the same step);
+ *   - streaming, Eq. (3);
+ *   - on every cut link, one curved-wall rule of Sec. 2.2: halfway
+ *     bounce-back, Filippova-Haenel (Eqs. 7-10), Mei-Luo-Shyy (Eqs. 7, 8,
+ *     10, 11), linear or quadratic Bouzidi (Eqs. 12, 13) or Zhao-Yong
+ *     (Eq. 14);
+ *   - at every boundary node, the leak of Eq. (15) and the correction of
+ *     scheme A (Eq. 18), scheme B (Eqs. 20-22) or Bao et al. (Eq. 23).
+ *
+ * Conventions
+ *   Lattice: D2Q9, directions 0 rest, 1 (+1,0), 2 (0,+1), 3 (-1,0),
+ *   4 (0,-1), 5 (+1,+1), 6 (-1,+1), 7 (-1,-1), 8 (+1,-1).
+ *   Host arrays of nodes are row-major with index y*nx + x.
+ *   The domain is periodic in x and y; walls are solid nodes.  A cut link
+ *   (x, y, dir) joins a fluid node to a solid node at (x, y) + e_dir; every
+ *   such adjacency must be listed exactly once.
+ *
+ * Ownership: the caller owns every array it passes; lbm_create_domain
+ *   copies what it needs and keeps no pointer.  The domain owns all device
+ *   memory until lbm_destroy.  Output arrays are caller-allocated.
+ *
+ * Errors: every call returns an lbm_status; nothing throws or aborts.  On
+ *   error the outputs are untouched and nothing is leaked.
+ *
+ * Threading: one host thread per domain at a time.  Several domains may
+ *   share a device and a stream.
+ */
+#ifndef LBM2P_H
+#define LBM2P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument or inconsistent geometry       */
+    LBM_ENOMEM = -2,     /* device or host allocation failed                 */
+    LBM_EDEVICE = -3,    /* a HIP runtime call failed                        */
+    LBM_ESINGULAR = -4,  /* Filippova-Haenel with q < 1/2 at tau = 1 (Eq. 9) */
+    LBM_EUNSTABLE = -5   /* a step produced a non-finite total mass          */
+} lbm_status;
+
+enum lbm_rule {
+    LBM_RULE_HALFWAY = 0,        /* f_abar(x_b,t+1) = f*_a(x_b,t)            */
+    LBM_RULE_FH = 1,             /* Eqs. 7-10                                */
+    LBM_RULE_MLS = 2,            /* Eqs. 7, 8, 10, 11                        */
+    LBM_RULE_IBB_LINEAR = 3,     /* Eq. 12                                   */
+    LBM_RULE_IBB_QUADRATIC = 4,  /* Eq. 13                                   */
+    LBM_RULE_ZHAO_YONG = 5       /* Eq. 14                                   */
+};
+
+enum lbm_fix {
+    LBM_FIX_NONE = 0,
+    LBM_FIX_A = 1,    /* Eq. 18: leak added to the rest population          */
+    LBM_FIX_B = 2,    /* Eqs. 20-22: fictitious density balancing the node  */
+    LBM_FIX_BAO = 3   /* Eq. 23: Bao et al.'s density (chi outside the sum) */
+};
+
+enum lbm_eos {
+    LBM_EOS_NONE = 0, /* single phase: no interaction force                */
+    LBM_EOS_EXP = 1,  /* psi = p0 exp(-p1/rho)                              */
+    LBM_EOS_CS = 2    /* Carnahan-Starling, p = (a, b, R, T):
+                         psi = sqrt(2 (p_CS(rho) - rho/3) / G)              */
+};
+
+enum lbm_collision { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
+
+enum lbm_storage {
+    LBM_STORE_F64 = 0,  /* FP64 populations, FP64 arithmetic               */
+    LBM_STORE_F32 = 1   /* FP32 populations, FP32 arithmetic; boundary
+                           sums and the total mass in FP64                 */
+};
+
+/* One cut link (40 bytes). */
+typedef struct {
+    int32_t x, y;       /* fluid boundary node x_b                          */
+    int32_t dir;        /* 1..8; x_b + e_dir is solid                       */
+    int32_t reserved;   /* must be 0                                        */
+    double q;           /* wall fraction of Eq. 6, 0 < q <= 1               */
+    double uw[2];       /* wall velocity at the cut point (0 for the paper's
+                           resting walls); only HALFWAY, FH, MLS accept it  */
+} lbm_link;
+
+typedef struct {
+    int32_t nx, ny;            /* lattice size, each >= 3                   */
+    const uint8_t *solid;      /* host, nx*ny, nonzero = solid node         */
+    const lbm_link *links;     /* host, nlinks cut links                    */
+    int64_t nlinks;
+    const double *rho_wall;    /* host, nx*ny virtual wall density read at
+                                  solid nodes (contact angle, Sec. 3.2);
+                                  NULL: rho_wall_const everywhere          */
+    double rho_wall_const;
+    int32_t eos;               /* enum lbm_eos                              */
+    int32_t collision;         /* enum lbm_collision                        */
+    double eos_param[4];       /* EXP: psi0, rho0.  CS: a, b, R, T          */
+    double G;                  /* interaction strength of Eq. 16 (< 0 is
+                                  attractive); ignored for EOS_NONE         */
+    double gravity[2];         /* body force per unit density               */
+    double tau;                /* relaxation time (> 1/2); for MRT the
+                                  shear rates mrt_s[7], mrt_s[8] must equal
+                                  1/tau                                     */
+    double mrt_s[9];           /* MRT rates, moments (rho, e, eps, jx, qx,
+                                  jy, qy, pxx, pxy) of Lallemand & Luo      */
+    int32_t rule;              /* enum lbm_rule                             */
+    int32_t fix;               /* enum lbm_fix; B and BAO need FH or MLS    */
+    int32_t storage;           /* enum lbm_storage                          */
+    int32_t reserved;          /* must be 0                                 */
+    const double *rho0;        /* host, nx*ny initial density (> 0 on fluid)*/
+    const double *ux0, *uy0;   /* host, nx*ny initial velocity, or NULL     */
+    int64_t history_capacity;  /* mass-history ring entries; 0 = 1048576   */
+    void *stream;              /* hipStream_t for all work, NULL = default  */
+    int32_t tile_w;            /* launch shape of the main kernel: columns
+                                  per workgroup (64, 128 or 256; 0 = auto)  */
+    int32_t tile_h;            /* rows per workgroup (0 = auto)             */
+} lbm_desc;
+
+typedef struct lbm_domain lbm_domain;
+
+/* Validate the descriptor, build the boundary tables, upload the state and
+ * compute f*(0) from f(0) = f_eq(rho0, u0).  Errors: LBM_EINVAL (sizes,
+ * tau <= 1/2, a bad or missing or duplicate link, q outside (0,1], a
+ * moving wall with a rule that does not support it, rho0 <= 0 on a fluid
+ * node, psi^2 < 0 at rho0 or at a wall density, FIX_B/BAO with a rule
+ * other than FH/MLS, MRT shear rates != 1/tau), LBM_ESINGULAR, LBM_ENOMEM,
+ * LBM_EDEVICE. */
+int lbm_create_domain(const lbm_desc *desc, lbm_domain **out);
+
+/* Advance n >= 0 steps and wait for them.  LBM_EUNSTABLE names the first
+ * step whose total mass was not finite (see lbm_unstable_step). */
+int lbm_step(lbm_domain *d, int64_t n);
+
+/* As lbm_step, without waiting; lbm_sync waits and reports the status. */
+int lbm_step_async(lbm_domain *d, int64_t n);
+int lbm_sync(lbm_domain *d);
+
+/* Density and velocity of Eq. 5 at the current time into host arrays of
+ * nx*ny doubles (any may be NULL); solid nodes get 0. */
+int lbm_moments(lbm_domain *d, double *rho, double *ux, double *uy);
+
+/* As lbm_moments into device arrays of nx*ny doubles, on the domain's
+ * stream, without waiting. */
+int lbm_moments_device(lbm_domain *d, double *rho, double *ux, double *uy);
+
+/* Total mass sum over fluid nodes of sum_a f_a at the current time (FP64). */
+int lbm_total_mass(lbm_domain *d, double *out);
+
+/* Current time step count. */
+int lbm_time(lbm_domain *d, int64_t *t);
+
+/* The last min(t+1, capacity, cap) total masses M(.) in time order. */
+int lbm_mass_history(lbm_domain *d, double *out, int64_t cap,
+                     int64_t *n_written);
+
+/* Step index of the first non-finite total mass, or -1. */
+int lbm_unstable_step(lbm_domain *d, int64_t *step);
+
+/* Checkpoint: with buf == NULL, *bytes receives the size; otherwise the
+ * state is written if *bytes is large enough (else LBM_EINVAL).  Restoring
+ * it into a domain built from the same descriptor resumes bit-exactly. */
+int lbm_get_state(lbm_domain *d, void *buf, size_t *bytes);
+int lbm_set_state(lbm_domain *d, const void *buf, size_t bytes);
+
+/* Per-kernel timing: with every > 0, lbm_step brackets the boundary and
+ * main launches of every every-th step with HIP events on the domain's
+ * stream (no host synchronisation until 1024 samples are pending);
+ * lbm_kernel_times returns the summed durations (ms) and sample counts
+ * since profiling was last set.  every = 0 switches it off. */
+int lbm_set_profiling(lbm_domain *d, int every);
+int lbm_kernel_times(lbm_domain *d, double *main_ms, int64_t *main_count,
+                     double *boundary_ms, int64_t *boundary_count);
+
+/* Facts about the built domain: [0] fluid nodes, [1] cut links,
+ * [2] boundary nodes, [3] bytes of device memory held, [4] tile_w,
+ * [5] tile_h, [6] main-kernel workgroups, [7] boundary-rule fallbacks
+ * (x_f or x_ff solid) taken per step. */
+int lbm_info(lbm_domain *d, int64_t out[8]);
+
+void lbm_destroy(lbm_domain *d);
+const char *lbm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM2P_H */

@@ -1,0 +1,42 @@
+// Launch interface between the host API and the kernels.  Each storage
+// precision is compiled in its own translation unit (launch_f64.hip with
+// exact left-to-right rounding, launch_f32.hip with fused multiply-adds).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+struct Ctx {
+    int nx, ny, pitch;
+    long long plane;
+    int eos, coll;
+    int tile_w, tile_h, nsegs, nblocks;
+    const uint8_t* flags;
+    void* psiw;
+    const int* side_idx;
+    double* side_mom;
+    double* side_f;
+    double* partial;
+    double* mom_out;
+    Phys<double> ph;  // converted to the compute type by the launcher
+    hipStream_t stream;
+};
+
+// one main pass src -> dst (or the moments of src when moments is set)
+void launch_main_f64(const Ctx& c, const void* src, void* dst, bool moments);
+void launch_main_f32(const Ctx& c, const void* src, void* dst, bool moments);
+// one boundary pass on cur
+void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
+void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
+// psi at walls and f(0) = f_eq(rho0, u0) scattered into buf
+void launch_init_f64(const Ctx& c, const double* rho_wall, const double* rho0,
+                     const double* ux0, const double* uy0, void* buf);
+void launch_init_f32(const Ctx& c, const double* rho_wall, const double* rho0,
+                     const double* ux0, const double* uy0, void* buf);
+void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
+                   long long* unstable);
+
+}  // namespace lbm

@@ -1,0 +1,23 @@
+// FP64 storage and arithmetic.  Built with -ffp-contract=off: every product
+// and sum rounds as written, in the order the method's formulas give it.
+#include "launch_impl.hpp"
+
+namespace lbm {
+
+void launch_main_f64(const Ctx& c, const void* src, void* dst, bool moments) {
+    main_any<double, double>(c, src, dst, moments);
+}
+void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
+    boundary_any<double>(c, cur, b, nblocks);
+}
+void launch_init_f64(const Ctx& c, const double* rw, const double* r0, const double* u0,
+                     const double* v0, void* buf) {
+    init_any<double, double>(c, rw, r0, u0, v0, buf);
+}
+void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
+                   long long* unstable) {
+    hipLaunchKernelGGL(k_reduce<0>, dim3(1), dim3(256), 0, c.stream, c.partial, c.nblocks,
+                       hist, slot, t, unstable);
+}
+
+}  // namespace lbm

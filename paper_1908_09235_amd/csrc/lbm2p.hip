@@ -1,0 +1,778 @@
+// Host side of the lbm2p C ABI (include/lbm2p.h): descriptor validation,
+// boundary tables, device memory, launches, checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm2p.h"
+#include "launch.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr uint64_t kStateMagic = 0x6c626d3270737431ULL;  // "lbm2pst1"
+constexpr int kProfPool = 1024;
+
+}  // namespace
+
+struct lbm_domain {
+    int nx = 0, ny = 0, pitch = 0;
+    long long plane = 0;
+    int storage = 0, eos = 0, coll = 0, rule = 0, fix = 0;
+    int tile_w = 0, tile_h = 0, nstrips = 0, nsegs = 0, nblocks = 0;
+    size_t esize = 8;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t* flags = nullptr;
+    void* psiw = nullptr;
+    int* side_idx = nullptr;
+    double* side_mom = nullptr;
+    double* side_f = nullptr;
+    int nslots = 0;
+    bool save_f = false;
+    double* partial = nullptr;
+    double* hist = nullptr;
+    long long* unstable = nullptr;
+    double* mom_out = nullptr;
+    int nb = 0, nl = 0;
+    int *bnode = nullptr, *bslot = nullptr, *bstart = nullptr, *ldir = nullptr,
+        *lkind = nullptr, *lghost = nullptr, *lxf = nullptr, *lxff = nullptr,
+        *lslotf = nullptr;
+    double *lc = nullptr, *luw = nullptr;
+    long long cap = 0, t = 0;
+    bool pending = false;
+    long long pending_t = 0;
+    hipStream_t stream = nullptr;
+    Phys<double> ph64{};
+    Phys<float> ph32{};
+    size_t bytes = 0;
+    long long fluid = 0, fallbacks = 0;
+    std::vector<void*> allocs;
+    int prof = 0;  // record every prof-th step (0: off)
+    int nrec = 0;
+    std::vector<hipEvent_t> ev;
+    double main_ms = 0, bnd_ms = 0;
+    long long main_n = 0, bnd_n = 0;
+};
+
+namespace {
+
+int dev_alloc(lbm_domain* d, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return LBM_ENOMEM;
+    }
+    d->allocs.push_back(*p);
+    d->bytes += bytes;
+    return LBM_OK;
+}
+
+template <typename T>
+int upload(lbm_domain* d, T** dst, const std::vector<T>& src) {
+    int rc = dev_alloc(d, reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+    if (rc) return rc;
+    if (!src.empty() &&
+        hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return LBM_EDEVICE;
+    return LBM_OK;
+}
+
+void free_domain(lbm_domain* d) {
+    if (!d) return;
+    for (void* p : d->allocs) (void)hipFree(p);
+    for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+    delete d;
+}
+
+inline int wrapi(int i, int n) { return ((i % n) + n) % n; }
+
+template <typename R>
+Phys<R> make_phys(const lbm_desc* s) {
+    Phys<R> p{};
+    p.G = R(s->G);
+    p.gx = R(s->gravity[0]);
+    p.gy = R(s->gravity[1]);
+    p.omega = R(1.0 / s->tau);
+    p.guo_pref = R(1.0 - 1.0 / (2.0 * s->tau));
+    p.e0 = R(s->eos_param[0]);
+    p.e1 = R(s->eos_param[1]);
+    p.e2 = R(s->eos_param[2]);
+    p.e3 = R(s->eos_param[3]);
+    for (int i = 0; i < 9; ++i) p.s[i] = R(s->mrt_s[i]);
+    return p;
+}
+
+double host_psi(int eos, const Phys<double>& p, double rho) {
+    if (eos == EOS_EXP) return psi_of<EOS_EXP, double>(rho, p);
+    if (eos == EOS_CS) return psi_of<EOS_CS, double>(rho, p);
+    return 0.0;
+}
+
+// ---------------------------------------------------------------- launches
+Ctx ctx(lbm_domain* d) {
+    Ctx c{};
+    c.nx = d->nx;
+    c.ny = d->ny;
+    c.pitch = d->pitch;
+    c.plane = d->plane;
+    c.eos = d->eos;
+    c.coll = d->coll;
+    c.tile_w = d->tile_w;
+    c.tile_h = d->tile_h;
+    c.nsegs = d->nsegs;
+    c.nblocks = d->nblocks;
+    c.flags = d->flags;
+    c.psiw = d->psiw;
+    c.side_idx = d->side_idx;
+    c.side_mom = d->side_mom;
+    c.side_f = d->side_f;
+    c.partial = d->partial;
+    c.mom_out = d->mom_out;
+    c.ph = d->ph64;
+    c.stream = d->stream;
+    return c;
+}
+
+void launch_main(lbm_domain* d, const void* src, void* dst, bool moments) {
+    if (d->storage == LBM_STORE_F64) launch_main_f64(ctx(d), src, dst, moments);
+    else launch_main_f32(ctx(d), src, dst, moments);
+}
+
+BndArgs bnd_args(lbm_domain* d) {
+    BndArgs b{};
+    b.nb = d->nb;
+    b.bnode = d->bnode;
+    b.bslot = d->bslot;
+    b.bstart = d->bstart;
+    b.ldir = d->ldir;
+    b.lkind = d->lkind;
+    b.lghost = d->lghost;
+    b.lxf = d->lxf;
+    b.lxff = d->lxff;
+    b.lslotf = d->lslotf;
+    b.lc = d->lc;
+    b.luw = d->luw;
+    b.side_mom = d->side_mom;
+    b.side_f = d->side_f;
+    b.plane = d->plane;
+    b.fix = d->fix;
+    b.partial = d->partial;
+    b.np = d->nblocks;
+    b.hist = d->hist;
+    b.unstable = d->unstable;
+    b.do_reduce = d->pending ? 1 : 0;
+    b.t = d->pending_t;
+    b.slot = d->pending_t % d->cap;
+    return b;
+}
+
+void launch_boundary(lbm_domain* d, void* cur) {
+    BndArgs b = bnd_args(d);
+    const int nbb = (d->nb + 255) / 256 + 1;
+    if (d->storage == LBM_STORE_F64) launch_boundary_f64(ctx(d), cur, b, nbb);
+    else launch_boundary_f32(ctx(d), cur, b, nbb);
+    d->pending = false;
+}
+
+void reduce_pending(lbm_domain* d) {
+    if (!d->pending) return;
+    launch_reduce(ctx(d), d->pending_t % d->cap, d->pending_t, d->hist, d->unstable);
+    d->pending = false;
+}
+
+int ensure_events(lbm_domain* d) {
+    while ((int)d->ev.size() < 4 * kProfPool) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return LBM_EDEVICE;
+        d->ev.push_back(e);
+    }
+    return LBM_OK;
+}
+
+// add the recorded launch durations to the totals and free the pool
+int harvest(lbm_domain* d) {
+    if (d->nrec == 0) return LBM_OK;
+    if (hipEventSynchronize(d->ev[4 * (d->nrec - 1) + 3]) != hipSuccess) return LBM_EDEVICE;
+    for (int i = 0; i < d->nrec; ++i) {
+        float a = 0, b = 0;
+        if (hipEventElapsedTime(&a, d->ev[4 * i + 0], d->ev[4 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, d->ev[4 * i + 2], d->ev[4 * i + 3]) != hipSuccess)
+            return LBM_EDEVICE;
+        d->bnd_ms += a;
+        d->main_ms += b;
+    }
+    d->bnd_n += d->nrec;
+    d->main_n += d->nrec;
+    d->nrec = 0;
+    return LBM_OK;
+}
+
+int run_steps(lbm_domain* d, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+        void* cur = d->f[d->cur];
+        void* nxt = d->f[d->cur ^ 1];
+        const bool rec = d->prof > 0 && (d->t % d->prof) == 0;
+        if (rec && d->nrec == kProfPool) {
+            int rc = harvest(d);
+            if (rc) return rc;
+        }
+        hipEvent_t* e = rec ? &d->ev[4 * d->nrec] : nullptr;
+        if (rec) (void)hipEventRecord(e[0], d->stream);
+        launch_boundary(d, cur);
+        if (rec) (void)hipEventRecord(e[1], d->stream);
+        if (rec) (void)hipEventRecord(e[2], d->stream);
+        launch_main(d, cur, nxt, false);
+        if (rec) (void)hipEventRecord(e[3], d->stream);
+        if (rec) d->nrec++;
+        d->cur ^= 1;
+        d->t += 1;
+        d->pending = true;
+        d->pending_t = d->t;
+    }
+    reduce_pending(d);
+    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+    return LBM_OK;
+}
+
+int check_unstable(lbm_domain* d) {
+    long long u = -1;
+    if (hipMemcpyAsync(&u, d->unstable, sizeof(u), hipMemcpyDeviceToHost, d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
+    return u >= 0 ? LBM_EUNSTABLE : LBM_OK;
+}
+
+// -------------------------------------------------------------- creation
+struct LinkRec {
+    int node;  // x_b index in y*nx + x
+    int dir;
+    int src;   // index in the descriptor
+};
+
+int validate_and_build(const lbm_desc* s, lbm_domain* d) {
+    const int nx = s->nx, ny = s->ny;
+    if (nx < 3 || ny < 3 || !s->solid || !s->rho0) return LBM_EINVAL;
+    if (!(s->tau > 0.5) || !std::isfinite(s->tau)) return LBM_EINVAL;
+    if (s->rule < 0 || s->rule > 5 || s->fix < 0 || s->fix > 3) return LBM_EINVAL;
+    if (s->eos < 0 || s->eos > 2 || s->collision < 0 || s->collision > 1) return LBM_EINVAL;
+    if (s->storage != LBM_STORE_F64 && s->storage != LBM_STORE_F32) return LBM_EINVAL;
+    if (s->reserved != 0) return LBM_EINVAL;
+    if ((s->fix == LBM_FIX_B || s->fix == LBM_FIX_BAO) && s->rule != LBM_RULE_FH &&
+        s->rule != LBM_RULE_MLS)
+        return LBM_EINVAL;
+    if (s->eos != LBM_EOS_NONE && (s->G == 0.0 || !std::isfinite(s->G))) return LBM_EINVAL;
+    if (s->collision == LBM_COLL_MRT) {
+        for (int i = 0; i < 9; ++i)
+            if (!(s->mrt_s[i] > 0.0 && s->mrt_s[i] < 2.0)) return LBM_EINVAL;
+        if (std::fabs(s->mrt_s[7] - 1.0 / s->tau) > 1e-12 ||
+            std::fabs(s->mrt_s[8] - 1.0 / s->tau) > 1e-12)
+            return LBM_EINVAL;
+    }
+    if (s->tile_w != 0 && s->tile_w != 64 && s->tile_w != 128 && s->tile_w != 256)
+        return LBM_EINVAL;
+    if (s->tile_h < 0) return LBM_EINVAL;
+    if ((long long)nx * ny >= (1LL << 30)) return LBM_EINVAL;
+    const long long N = (long long)nx * ny;
+    auto solid = [&](long long i) { return s->solid[i] != 0; };
+    d->ph64 = make_phys<double>(s);
+    d->ph32 = make_phys<float>(s);
+    // wall densities
+    for (long long i = 0; i < N; ++i) {
+        if (!solid(i)) continue;
+        const double rw = s->rho_wall ? s->rho_wall[i] : s->rho_wall_const;
+        if (!std::isfinite(rw)) return LBM_EINVAL;
+        if (s->eos != LBM_EOS_NONE) {
+            if (!(rw > 0.0) || !std::isfinite(host_psi(s->eos, d->ph64, rw))) return LBM_EINVAL;
+        }
+    }
+    // links
+    const long long L = s->nlinks;
+    if (L < 0 || (L > 0 && !s->links)) return LBM_EINVAL;
+    std::vector<LinkRec> recs((size_t)L);
+    bool singular = false;
+    for (long long k = 0; k < L; ++k) {
+        const lbm_link& l = s->links[k];
+        if (l.x < 0 || l.x >= nx || l.y < 0 || l.y >= ny || l.dir < 1 || l.dir > 8 ||
+            l.reserved != 0)
+            return LBM_EINVAL;
+        const long long b = (long long)l.y * nx + l.x;
+        const long long xs = (long long)wrapi(l.y + cy(l.dir), ny) * nx + wrapi(l.x + cx(l.dir), nx);
+        if (solid(b) || !solid(xs)) return LBM_EINVAL;
+        if (!(l.q > 0.0 && l.q <= 1.0)) return LBM_EINVAL;
+        if (!std::isfinite(l.uw[0]) || !std::isfinite(l.uw[1])) return LBM_EINVAL;
+        const bool moving = l.uw[0] != 0.0 || l.uw[1] != 0.0;
+        if (moving && !(s->rule == LBM_RULE_HALFWAY || s->rule == LBM_RULE_FH ||
+                        s->rule == LBM_RULE_MLS))
+            return LBM_EINVAL;
+        if (moving && s->fix == LBM_FIX_BAO) return LBM_EINVAL;
+        if (s->rule == LBM_RULE_FH && l.q < 0.5 && std::fabs(s->tau - 1.0) < 1e-12)
+            singular = true;
+        recs[k] = LinkRec{(int)b, l.dir, (int)k};
+    }
+    if (singular) return LBM_ESINGULAR;
+    std::sort(recs.begin(), recs.end(), [](const LinkRec& a, const LinkRec& b) {
+        return a.node != b.node ? a.node < b.node : a.dir < b.dir;
+    });
+    for (long long k = 1; k < L; ++k)
+        if (recs[k].node == recs[k - 1].node && recs[k].dir == recs[k - 1].dir) return LBM_EINVAL;
+    long long count = 0, fluid = 0;
+    for (long long i = 0; i < N; ++i) {
+        if (solid(i)) continue;
+        ++fluid;
+        const int x = (int)(i % nx), y = (int)(i / nx);
+        for (int a = 1; a < 9; ++a)
+            if (solid((long long)wrapi(y + cy(a), ny) * nx + wrapi(x + cx(a), nx))) ++count;
+    }
+    if (count != L) return LBM_EINVAL;
+    // initial state
+    for (long long i = 0; i < N; ++i) {
+        if (solid(i)) continue;
+        const double r = s->rho0[i];
+        const double vx = s->ux0 ? s->ux0[i] : 0.0, vy = s->uy0 ? s->uy0[i] : 0.0;
+        if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(vx) || !std::isfinite(vy))
+            return LBM_EINVAL;
+        if (s->eos == LBM_EOS_CS && !std::isfinite(host_psi(s->eos, d->ph64, r)))
+            return LBM_EINVAL;
+    }
+    d->fluid = fluid;
+
+    // ---- layout
+    d->nx = nx;
+    d->ny = ny;
+    d->pitch = (nx + 63) / 64 * 64;
+    d->plane = (long long)d->pitch * ny + 256;  // stagger the nine planes
+    d->storage = s->storage;
+    d->esize = s->storage == LBM_STORE_F64 ? 8 : 4;
+    d->eos = s->eos;
+    d->coll = s->collision;
+    d->rule = s->rule;
+    d->fix = s->fix;
+    d->tile_w = s->tile_w ? s->tile_w : (nx >= 256 ? 256 : (nx > 64 ? 128 : 64));
+    d->tile_h = s->tile_h ? s->tile_h : 16;
+    d->nstrips = (nx + d->tile_w - 1) / d->tile_w;
+    d->nsegs = (ny + d->tile_h - 1) / d->tile_h;
+    d->nblocks = d->nstrips * d->nsegs;
+    d->cap = s->history_capacity > 0 ? s->history_capacity : (1LL << 20);
+    d->stream = static_cast<hipStream_t>(s->stream);
+    const int P = d->pitch;
+    auto pidx = [&](int x, int y) { return y * P + x; };
+
+    // ---- boundary tables
+    std::vector<uint8_t> flags((size_t)P * ny, 0);
+    std::vector<int> side_idx((size_t)P * ny, -1);
+    for (long long i = 0; i < N; ++i)
+        if (solid(i)) flags[pidx((int)(i % nx), (int)(i / nx))] |= FL_SOLID;
+    d->save_f = s->rule == LBM_RULE_ZHAO_YONG;
+    int nslots = 0;
+    auto slot_of = [&](int x, int y) {
+        const int p = pidx(x, y);
+        if (side_idx[p] < 0) side_idx[p] = nslots++;
+        flags[p] |= FL_SAVE_MOM;
+        return side_idx[p];
+    };
+    std::vector<int> bnode, bslot, bstart, ldir, lkind, lghost, lxf, lxff, lslotf;
+    std::vector<double> lc, luw;
+    const double tau = s->tau;
+    long long fallbacks = 0;
+    for (long long k = 0; k < L; ++k) {
+        const LinkRec& r = recs[k];
+        const int x = r.node % nx, y = r.node / nx, a = r.dir;
+        if (k == 0 || r.node != recs[k - 1].node) {
+            bstart.push_back((int)k);
+            bnode.push_back(pidx(x, y));
+            bslot.push_back(slot_of(x, y));
+            if (d->save_f) flags[pidx(x, y)] |= FL_SAVE_F;
+        }
+        const lbm_link& l = s->links[r.src];
+        const int xf = wrapi(x - cx(a), nx), yf = wrapi(y - cy(a), ny);
+        const int xff = wrapi(x - 2 * cx(a), nx), yff = wrapi(y - 2 * cy(a), ny);
+        const bool f_ok = !solid((long long)yf * nx + xf);
+        const bool ff_ok = f_ok && !solid((long long)yff * nx + xff);
+        const double q = l.q;
+        double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int kind = LK_HALFWAY, sf = -1;
+        switch (s->rule) {
+        case LBM_RULE_HALFWAY:
+            kind = LK_HALFWAY;
+            break;
+        case LBM_RULE_FH:
+        case LBM_RULE_MLS:
+            if (q < 0.5) {
+                if (s->rule == LBM_RULE_FH) {
+                    kind = LK_CHI_UB;
+                    c[3] = (2.0 * q - 1.0) / (tau - 1.0);
+                } else {
+                    c[3] = (2.0 * q - 1.0) / (tau - 2.0);
+                    if (f_ok) {
+                        kind = LK_CHI_UF;
+                        sf = slot_of(xf, yf);
+                    } else {
+                        kind = LK_CHI_UB;
+                        ++fallbacks;
+                    }
+                }
+            } else {
+                kind = LK_CHI_EXT;
+                c[3] = (2.0 * q - 1.0) / tau;
+                c[4] = (q - 1.0) / q;
+                c[5] = l.uw[0] / q;
+                c[6] = l.uw[1] / q;
+            }
+            break;
+        case LBM_RULE_IBB_LINEAR:
+        case LBM_RULE_IBB_QUADRATIC: {
+            const bool quad = s->rule == LBM_RULE_IBB_QUADRATIC;
+            if (quad && q < 0.5 && ff_ok) {
+                kind = LK_QUAD_F;
+                c[0] = q * (1.0 + 2.0 * q);
+                c[1] = 1.0 - 4.0 * q * q;
+                c[2] = q * (1.0 - 2.0 * q);
+            } else if (quad && q >= 0.5 && f_ok) {
+                kind = LK_QUAD_B;
+                c[0] = 1.0 / (q * (2.0 * q + 1.0));
+                c[1] = (2.0 * q - 1.0) / q;
+                c[2] = (2.0 * q - 1.0) / (2.0 * q + 1.0);
+            } else if (q < 0.5 && f_ok) {
+                if (quad) ++fallbacks;
+                kind = LK_LIN_F;
+                c[0] = 2.0 * q;
+                c[1] = 1.0 - 2.0 * q;
+            } else {
+                if (quad || q < 0.5) ++fallbacks;
+                kind = LK_LIN_B;
+                c[0] = 1.0 / (2.0 * q);
+                c[1] = (2.0 * q - 1.0) / (2.0 * q);
+            }
+            break;
+        }
+        case LBM_RULE_ZHAO_YONG:
+            kind = LK_ZY;
+            c[0] = 2.0 * q / (1.0 + 2.0 * q);
+            c[1] = 1.0 / (1.0 + 2.0 * q);
+            break;
+        }
+        ldir.push_back(a);
+        lkind.push_back(kind);
+        lghost.push_back(pidx(wrapi(x + cx(a), nx), wrapi(y + cy(a), ny)));
+        lxf.push_back(f_ok ? pidx(xf, yf) : -1);
+        lxff.push_back(ff_ok ? pidx(xff, yff) : -1);
+        lslotf.push_back(sf);
+        for (int j = 0; j < 8; ++j) lc.push_back(c[j]);
+        luw.push_back(l.uw[0]);
+        luw.push_back(l.uw[1]);
+    }
+    bstart.push_back((int)L);
+    d->nb = (int)bnode.size();
+    d->nl = (int)L;
+    d->nslots = nslots;
+    d->fallbacks = fallbacks;
+
+    // ---- device memory
+    int rc;
+    const size_t fbytes = (size_t)9 * d->plane * d->esize;
+    if ((rc = dev_alloc(d, &d->f[0], fbytes))) return rc;
+    if ((rc = dev_alloc(d, &d->f[1], fbytes))) return rc;
+    if (hipMemset(d->f[0], 0, fbytes) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemset(d->f[1], 0, fbytes) != hipSuccess) return LBM_EDEVICE;
+    if ((rc = upload(d, &d->flags, flags))) return rc;
+    if ((rc = upload(d, &d->side_idx, side_idx))) return rc;
+    if ((rc = dev_alloc(d, &d->psiw, (size_t)P * ny * d->esize))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->side_mom, (size_t)3 * std::max(nslots, 1) * 8))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->side_f,
+                        (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8)))
+        return rc;
+    if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->nblocks * 8))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
+    if ((rc = upload(d, &d->bnode, bnode))) return rc;
+    if ((rc = upload(d, &d->bslot, bslot))) return rc;
+    if ((rc = upload(d, &d->bstart, bstart))) return rc;
+    if ((rc = upload(d, &d->ldir, ldir))) return rc;
+    if ((rc = upload(d, &d->lkind, lkind))) return rc;
+    if ((rc = upload(d, &d->lghost, lghost))) return rc;
+    if ((rc = upload(d, &d->lxf, lxf))) return rc;
+    if ((rc = upload(d, &d->lxff, lxff))) return rc;
+    if ((rc = upload(d, &d->lslotf, lslotf))) return rc;
+    if ((rc = upload(d, &d->lc, lc))) return rc;
+    if ((rc = upload(d, &d->luw, luw))) return rc;
+    const long long minus1 = -1;
+    if (hipMemcpy(d->unstable, &minus1, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemset(d->hist, 0, (size_t)d->cap * 8) != hipSuccess) return LBM_EDEVICE;
+
+    // ---- initial state: psi at walls, f(0) scattered, f*(0) by one main pass
+    std::vector<double> rw((size_t)N), r0((size_t)N), u0((size_t)N, 0.0), v0((size_t)N, 0.0);
+    for (long long i = 0; i < N; ++i) {
+        rw[i] = s->rho_wall ? s->rho_wall[i] : s->rho_wall_const;
+        r0[i] = s->rho0[i];
+        if (s->ux0) u0[i] = s->ux0[i];
+        if (s->uy0) v0[i] = s->uy0[i];
+    }
+    double *drw = nullptr, *dr0 = nullptr, *du0 = nullptr, *dv0 = nullptr;
+    if ((rc = upload(d, &drw, rw))) return rc;
+    if ((rc = upload(d, &dr0, r0))) return rc;
+    if ((rc = upload(d, &du0, u0))) return rc;
+    if ((rc = upload(d, &dv0, v0))) return rc;
+    if (d->storage == LBM_STORE_F64) launch_init_f64(ctx(d), drw, dr0, du0, dv0, d->f[1]);
+    else launch_init_f32(ctx(d), drw, dr0, du0, dv0, d->f[1]);
+    launch_main(d, d->f[1], d->f[0], false);
+    d->cur = 0;
+    d->t = 0;
+    d->pending = true;
+    d->pending_t = 0;
+    reduce_pending(d);
+    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+    if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
+    // the initial fields are no longer needed
+    for (double* p : {drw, dr0, du0, dv0}) {
+        (void)hipFree(p);
+        d->allocs.erase(std::find(d->allocs.begin(), d->allocs.end(), (void*)p));
+        d->bytes -= (size_t)N * 8;
+    }
+    return check_unstable(d);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create_domain(const lbm_desc* desc, lbm_domain** out) {
+    if (!desc || !out) return LBM_EINVAL;
+    lbm_domain* d = new (std::nothrow) lbm_domain();
+    if (!d) return LBM_ENOMEM;
+    int rc = validate_and_build(desc, d);
+    if (rc != LBM_OK) {
+        free_domain(d);
+        return rc;
+    }
+    *out = d;
+    return LBM_OK;
+}
+
+int lbm_step_async(lbm_domain* d, int64_t n) {
+    if (!d || n < 0) return LBM_EINVAL;
+    if (n == 0) return LBM_OK;
+    return run_steps(d, n);
+}
+
+int lbm_sync(lbm_domain* d) {
+    if (!d) return LBM_EINVAL;
+    return check_unstable(d);
+}
+
+int lbm_step(lbm_domain* d, int64_t n) {
+    int rc = lbm_step_async(d, n);
+    if (rc != LBM_OK) return rc;
+    return lbm_sync(d);
+}
+
+int lbm_moments_device(lbm_domain* d, double* rho, double* ux, double* uy) {
+    if (!d) return LBM_EINVAL;
+    const size_t nn = (size_t)d->nx * d->ny;
+    if (!d->mom_out) {
+        int rc = dev_alloc(d, (void**)&d->mom_out, 3 * nn * 8);
+        if (rc) return rc;
+    }
+    launch_main(d, d->f[d->cur ^ 1], nullptr, true);
+    if (rho && hipMemcpyAsync(rho, d->mom_out, nn * 8, hipMemcpyDeviceToDevice, d->stream))
+        return LBM_EDEVICE;
+    if (ux && hipMemcpyAsync(ux, d->mom_out + nn, nn * 8, hipMemcpyDeviceToDevice, d->stream))
+        return LBM_EDEVICE;
+    if (uy && hipMemcpyAsync(uy, d->mom_out + 2 * nn, nn * 8, hipMemcpyDeviceToDevice, d->stream))
+        return LBM_EDEVICE;
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+int lbm_moments(lbm_domain* d, double* rho, double* ux, double* uy) {
+    if (!d) return LBM_EINVAL;
+    const size_t nn = (size_t)d->nx * d->ny;
+    if (!d->mom_out) {
+        int rc = dev_alloc(d, (void**)&d->mom_out, 3 * nn * 8);
+        if (rc) return rc;
+    }
+    launch_main(d, d->f[d->cur ^ 1], nullptr, true);
+    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+    double* outs[3] = {rho, ux, uy};
+    for (int k = 0; k < 3; ++k)
+        if (outs[k] && hipMemcpyAsync(outs[k], d->mom_out + k * nn, nn * 8,
+                                      hipMemcpyDeviceToHost, d->stream) != hipSuccess)
+            return LBM_EDEVICE;
+    return hipStreamSynchronize(d->stream) == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+int lbm_total_mass(lbm_domain* d, double* out) {
+    if (!d || !out) return LBM_EINVAL;
+    double m = 0;
+    if (hipMemcpyAsync(&m, d->hist + d->t % d->cap, 8, hipMemcpyDeviceToHost, d->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    *out = m;
+    return LBM_OK;
+}
+
+int lbm_time(lbm_domain* d, int64_t* t) {
+    if (!d || !t) return LBM_EINVAL;
+    *t = d->t;
+    return LBM_OK;
+}
+
+int lbm_mass_history(lbm_domain* d, double* out, int64_t cap, int64_t* n_written) {
+    if (!d || !out || cap < 0 || !n_written) return LBM_EINVAL;
+    const long long avail = std::min<long long>(d->t + 1, d->cap);
+    const long long n = std::min<long long>(avail, cap);
+    std::vector<double> ring((size_t)d->cap);
+    if (hipMemcpyAsync(ring.data(), d->hist, (size_t)d->cap * 8, hipMemcpyDeviceToHost,
+                       d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    const long long first = d->t + 1 - n;
+    for (long long i = 0; i < n; ++i) out[i] = ring[(size_t)((first + i) % d->cap)];
+    *n_written = n;
+    return LBM_OK;
+}
+
+int lbm_unstable_step(lbm_domain* d, int64_t* step) {
+    if (!d || !step) return LBM_EINVAL;
+    long long u = -1;
+    if (hipMemcpyAsync(&u, d->unstable, 8, hipMemcpyDeviceToHost, d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    *step = u;
+    return LBM_OK;
+}
+
+static size_t state_bytes(const lbm_domain* d) {
+    return 8 * 4 + 2 * (size_t)9 * d->plane * d->esize + (size_t)3 * std::max(d->nslots, 1) * 8 +
+           (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8 + (size_t)d->cap * 8 + 8;
+}
+
+int lbm_get_state(lbm_domain* d, void* buf, size_t* bytes) {
+    if (!d || !bytes) return LBM_EINVAL;
+    const size_t need = state_bytes(d);
+    if (!buf) {
+        *bytes = need;
+        return LBM_OK;
+    }
+    if (*bytes < need) return LBM_EINVAL;
+    if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
+    char* p = static_cast<char*>(buf);
+    const uint64_t hdr[4] = {kStateMagic, (uint64_t)d->t, ((uint64_t)d->nx << 32 | (uint64_t)d->ny),
+                             (uint64_t)d->storage};
+    std::memcpy(p, hdr, sizeof(hdr));
+    p += sizeof(hdr);
+    const size_t fb = (size_t)9 * d->plane * d->esize;
+    const size_t sm = (size_t)3 * std::max(d->nslots, 1) * 8;
+    const size_t sf = (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8;
+    if (hipMemcpy(p, d->f[d->cur], fb, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    p += fb;
+    if (hipMemcpy(p, d->f[d->cur ^ 1], fb, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    p += fb;
+    if (hipMemcpy(p, d->side_mom, sm, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    p += sm;
+    if (hipMemcpy(p, d->side_f, sf, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    p += sf;
+    if (hipMemcpy(p, d->hist, (size_t)d->cap * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return LBM_EDEVICE;
+    p += (size_t)d->cap * 8;
+    if (hipMemcpy(p, d->unstable, 8, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    *bytes = need;
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
+    if (!d || !buf || bytes != state_bytes(d)) return LBM_EINVAL;
+    const char* p = static_cast<const char*>(buf);
+    uint64_t hdr[4];
+    std::memcpy(hdr, p, sizeof(hdr));
+    if (hdr[0] != kStateMagic || hdr[2] != ((uint64_t)d->nx << 32 | (uint64_t)d->ny) ||
+        hdr[3] != (uint64_t)d->storage)
+        return LBM_EINVAL;
+    p += sizeof(hdr);
+    if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
+    const size_t fb = (size_t)9 * d->plane * d->esize;
+    const size_t sm = (size_t)3 * std::max(d->nslots, 1) * 8;
+    const size_t sf = (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8;
+    d->cur = 0;
+    if (hipMemcpy(d->f[0], p, fb, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    p += fb;
+    if (hipMemcpy(d->f[1], p, fb, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    p += fb;
+    if (hipMemcpy(d->side_mom, p, sm, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    p += sm;
+    if (hipMemcpy(d->side_f, p, sf, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    p += sf;
+    if (hipMemcpy(d->hist, p, (size_t)d->cap * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return LBM_EDEVICE;
+    p += (size_t)d->cap * 8;
+    if (hipMemcpy(d->unstable, p, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    d->t = (long long)hdr[1];
+    d->pending = false;
+    d->pending_t = d->t;
+    return LBM_OK;
+}
+
+int lbm_set_profiling(lbm_domain* d, int every) {
+    if (!d || every < 0) return LBM_EINVAL;
+    int rc = harvest(d);
+    if (rc) return rc;
+    if (every) {
+        rc = ensure_events(d);
+        if (rc) return rc;
+    }
+    d->prof = every;
+    d->main_ms = d->bnd_ms = 0;
+    d->main_n = d->bnd_n = 0;
+    return LBM_OK;
+}
+
+int lbm_kernel_times(lbm_domain* d, double* main_ms, int64_t* main_count, double* boundary_ms,
+                     int64_t* boundary_count) {
+    if (!d) return LBM_EINVAL;
+    int rc = harvest(d);
+    if (rc) return rc;
+    if (main_ms) *main_ms = d->main_ms;
+    if (main_count) *main_count = d->main_n;
+    if (boundary_ms) *boundary_ms = d->bnd_ms;
+    if (boundary_count) *boundary_count = d->bnd_n;
+    return LBM_OK;
+}
+
+int lbm_info(lbm_domain* d, int64_t out[8]) {
+    if (!d || !out) return LBM_EINVAL;
+    out[0] = d->fluid;
+    out[1] = d->nl;
+    out[2] = d->nb;
+    out[3] = (int64_t)d->bytes;
+    out[4] = d->tile_w;
+    out[5] = d->tile_h;
+    out[6] = d->nblocks;
+    out[7] = d->fallbacks;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_domain* d) {
+    if (!d) return;
+    (void)hipStreamSynchronize(d->stream);
+    free_domain(d);
+}
+
+const char* lbm_status_string(int status) {
+    switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_ESINGULAR: return "singular boundary parameter (Filippova-Haenel, q < 1/2, tau = 1)";
+    case LBM_EUNSTABLE: return "non-finite total mass";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects
+invalid descriptors with the same codes as the oracle (validation happens
+before any device call, so these run without a GPU)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from lbm_inputs import configs as cfg
+from oracle import core as ora
+from tests._lib import ensure_built, header_symbols
+
+
+@pytest.fixture(scope="module")
+def L():
+    ensure_built()
+    from paper_1908_09235_amd import lbm
+    return lbm
+
+
+def test_library_exports_every_declared_symbol(L):
+    syms = header_symbols()
+    assert len(syms) >= 17
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for s in syms:
+        assert hasattr(raw, s), s
+    assert set(syms) == set(L.EXPORTS)
+
+
+def test_status_strings(L):
+    for code in range(-5, 1):
+        assert L.lbm_status_string(code)
+    assert "unknown" in L.lbm_status_string(-99)
+
+
+def test_null_arguments_are_rejected(L):
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    assert lib.lbm_create_domain(None, ctypes.byref(h)) == L.LBM_EINVAL
+    assert lib.lbm_step(None, 1) == L.LBM_EINVAL
+    assert lib.lbm_total_mass(None, None) == L.LBM_EINVAL
+    assert lib.lbm_moments(None, None, None, None) == L.LBM_EINVAL
+    n = ctypes.c_size_t()
+    assert lib.lbm_get_state(None, None, ctypes.byref(n)) == L.LBM_EINVAL
+    lib.lbm_destroy(None)
+
+
+def _bad_problem(bad):
+    p = cfg.cfg1("mls", "A")
+    lk = p.links.copy()
+    if bad == "q0":
+        lk["q"][3] = 0.0
+        return p.with_(links=lk)
+    if bad == "q_gt_1":
+        lk["q"][3] = 1.0000001
+        return p.with_(links=lk)
+    if bad == "missing":
+        return p.with_(links=lk[1:])
+    if bad == "dup":
+        return p.with_(links=np.concatenate([lk, lk[:1]]))
+    if bad == "fluid_target":
+        lk["dir"][0] = 1 if lk["dir"][0] != 1 else 3
+        return p.with_(links=lk)
+    if bad == "tau":
+        return p.with_(tau=0.5)
+    if bad == "fh_pole":
+        return p.with_(rule="fh", tau=1.0)
+    if bad == "fixb_rule":
+        return p.with_(rule="ibb_linear", fix="B")
+    if bad == "rho0":
+        r = p.rho0.copy()
+        r[100, 5] = -1.0
+        return p.with_(rho0=r)
+    if bad == "cs_psi":
+        r = p.rho0.copy()
+        r[100, 5] = 0.6
+        return p.with_(rho0=r)
+    if bad == "moving_ibb":
+        lk["uwx"][0] = 0.01
+        return p.with_(links=lk, rule="ibb_linear")
+    if bad == "mrt_rates":
+        return p.with_(collision="mrt", mrt_s=(1.0,) * 7 + (1.5, 1.5))
+    if bad == "wall_density":
+        rw = p.rho_wall.copy()
+        rw[:] = -1.0
+        return p.with_(rho_wall=rw)
+    raise AssertionError(bad)
+
+
+BAD = ["q0", "q_gt_1", "missing", "dup", "fluid_target", "tau", "fh_pole",
+       "fixb_rule", "rho0", "cs_psi", "moving_ibb", "mrt_rates", "wall_density"]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_descriptors_match_oracle_codes(L, bad):
+    p = _bad_problem(bad)
+    with pytest.raises(ora.OracleError) as eo:
+        ora.Oracle(p)
+    with pytest.raises(L.LbmError) as eg:
+        L.lbm_create_domain(p, storage="f64")
+    assert eg.value.code == eo.value.code
+    assert eg.value.code in (L.LBM_EINVAL, L.LBM_ESINGULAR)
+
+
+def test_bad_launch_shape_and_storage_are_rejected(L):
+    p = cfg.cfg1()
+    for kw in (dict(tile_w=96), dict(tile_h=-1)):
+        with pytest.raises(L.LbmError) as e:
+            L.lbm_create_domain(p, **kw)
+        assert e.value.code == L.LBM_EINVAL
+    d, keep = L.make_desc(p)
+    d.storage = 7
+    h = ctypes.c_void_p()
+    assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+    d.storage = 0
+    d.reserved = 1
+    assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL

@@ -1,0 +1,256 @@
+"""HIP library vs the FP64 CPU oracle, element by element, on the same seeded
+inputs.  Bar: FP64 storage within 1e-12 (max-norm relative, rho and u over
+fluid nodes) after 1000 steps; FP32 storage within 1e-5; mass histories
+within 1e-13 relative in FP64.  Full-size (2048^2) cases are checked through
+properties that hold at any size."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from lbm_inputs import configs as cfg
+from lbm_inputs import geometry as geo
+from lbm_inputs.problem import Problem
+from oracle import core as ora
+from tests._lib import rel_err
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+MASS_TOL = 1e-13
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_09235_amd import lbm
+    lbm.lib()  # raises if the library is missing
+    return lbm
+
+
+def gpu_run(L, p, steps, storage="f64", **kw):
+    say(f"[gpu] {p.name} rule={p.rule} fix={p.fix} {storage} steps={steps} {kw}")
+    with L.Domain(p, storage=storage, **kw) as d:
+        d.step(steps)
+        r, ux, uy = d.moments()
+        hist = d.mass_history()
+    return r, ux, uy, hist
+
+
+_ORACLE = {}
+
+
+def oracle_run(p, steps, key=None):
+    key = key or (p.name, p.rule, p.fix, p.collision, p.tau, steps)
+    if key not in _ORACLE:
+        o = ora.Oracle(p)
+        m0 = o.total_mass()
+        h = o.step(steps)
+        r, ux, uy = o.moments()
+        _ORACLE[key] = (r, ux, uy, np.concatenate([[m0], h]))
+    return _ORACLE[key]
+
+
+def compare(p, g, o, tol, mass_tol=None):
+    fl = ~p.solid.astype(bool)
+    e = [rel_err(g[i], o[i], fl) for i in range(3)]
+    say(f"    rel err rho {e[0]:.3e} ux {e[1]:.3e} uy {e[2]:.3e}")
+    assert max(e) <= tol, e
+    assert np.all(g[0][~fl] == 0)
+    if mass_tol is not None:
+        gh, oh = g[3], o[3]
+        assert len(gh) == len(oh)
+        dm = np.max(np.abs(gh - oh) / np.abs(oh))
+        say(f"    mass history rel diff {dm:.3e}")
+        assert dm <= mass_tol
+
+
+CFG1_CASES = [("mls", "A"), ("mls", "B"), ("ibb_linear", "A"),
+              ("ibb_quadratic", "A"), ("halfway", "none"), ("mls", "none"),
+              ("ibb_linear", "none"), ("ibb_quadratic", "none"), ("mls", "bao")]
+
+
+@pytest.mark.parametrize("rule,fix", CFG1_CASES)
+def test_cfg1_fp64_1000_steps(L, rule, fix):
+    """Droplet on a cylinder, 128^2, CS EOS at 0.86 Tc, BGK tau = 1."""
+    p = cfg.cfg1(rule, fix)
+    compare(p, gpu_run(L, p, 1000), oracle_run(p, 1000), F64_TOL, MASS_TOL)
+
+
+@pytest.mark.parametrize("fix,steps", [("none", 25), ("A", 5)])
+def test_cfg1_zhao_yong_before_breakdown(L, fix, steps):
+    """Zhao-Yong drives this droplet unstable within a few steps (the oracle
+    breaks at steps 31 and 7); compare over the stable window."""
+    p = cfg.cfg1("zhao_yong", fix)
+    compare(p, gpu_run(L, p, steps), oracle_run(p, steps), F64_TOL, MASS_TOL)
+
+
+@pytest.mark.parametrize("rule,fix", [("mls", "A"), ("mls", "B"),
+                                      ("ibb_quadratic", "A"), ("mls", "none")])
+def test_cfg1_fp32_1000_steps(L, rule, fix):
+    p = cfg.cfg1(rule, fix)
+    g = gpu_run(L, p, 1000, storage="f32")
+    compare(p, g, oracle_run(p, 1000), F32_TOL)
+    m0 = g[3][0]
+    say(f"    fp32 mass drift {(g[3][-1] - m0) / m0:.3e}")
+
+
+def test_moments_at_time_zero(L):
+    p = cfg.cfg1("mls", "B")
+    o = ora.Oracle(p)
+    r, ux, uy = o.moments()
+    with L.Domain(p) as d:
+        g = d.moments()
+        m = d.total_mass()
+    compare(p, (*g, None), (r, ux, uy, None), 1e-15)
+    assert abs(m - o.total_mass()) / m < 1e-14
+
+
+@pytest.mark.parametrize("rule,q", [("zhao_yong", 0.3), ("ibb_quadratic", 0.3),
+                                    ("mls", 0.7), ("ibb_linear", 0.8)])
+def test_static_gravity_parity(L, rule, q):
+    """Sec. 3.1's single-phase test: flat walls with fraction q, gravity."""
+    p = cfg.static_gravity(q, rule=rule)
+    compare(p, gpu_run(L, p, 1000), oracle_run(p, 1000), F64_TOL, MASS_TOL)
+
+
+@pytest.mark.parametrize("fix", ["none", "A", "B"])
+def test_couette_moving_wall_parity(L, fix):
+    p = cfg.couette(10, rule="mls", fix=fix)
+    compare(p, gpu_run(L, p, 1000), oracle_run(p, 1000), F64_TOL, MASS_TOL)
+
+
+def test_fh_couette_parity(L):
+    p = cfg.couette(10, rule="fh", fix="A", tau=0.7)
+    compare(p, gpu_run(L, p, 1000), oracle_run(p, 1000), F64_TOL, MASS_TOL)
+
+
+def test_mrt_droplet_parity(L):
+    """The 2048^2 MRT workload scaled down to 256^2 (MLS + B, tau = 0.8)."""
+    p = cfg.cfg2a(scale=2.0)
+    compare(p, gpu_run(L, p, 400), oracle_run(p, 400), F64_TOL, MASS_TOL)
+    compare(p, gpu_run(L, p, 400, storage="f32"), oracle_run(p, 400), F32_TOL)
+
+
+def test_exp_eos_free_droplet_parity(L):
+    """psi = exp(-1/rho), G = -10/3 (Sec. 3.2); no walls."""
+    p = cfg.free_droplet(64, 14.0, eos="exp")
+    compare(p, gpu_run(L, p, 600), oracle_run(p, 600), F64_TOL, MASS_TOL)
+
+
+def _ragged_problem(nx=67, ny=53, rule="ibb_quadratic", fix="A"):
+    shapes = [geo.Circle(20.3, 17.6, 8.4), geo.Circle(47.1, 33.2, 11.7)]
+    solid, owner, links = geo.build(nx, ny, shapes)
+    rho0 = geo.tanh_disc(nx, ny, 20.3, 17.6 + 8.4, 10.0, 0.269941, 0.024515, 4.0)
+    rho0 = np.where(solid.astype(bool), 0.05, rho0)
+    return Problem(nx=nx, ny=ny, solid=solid, links=links, rho0=rho0,
+                   rho_wall=np.full((ny, nx), 0.05), eos="cs",
+                   eos_params=cfg.cs_params(0.86), G=-1.0, tau=0.9,
+                   mrt_s=cfg.mrt_rates(0.9), rule=rule, fix=fix, name="ragged")
+
+
+@pytest.mark.parametrize("tw,th", [(64, 16), (128, 7), (256, 53), (64, 1)])
+def test_ragged_tiles_parity(L, tw, th):
+    """67 x 53: a 3-column strip tail and a short last segment."""
+    p = _ragged_problem()
+    compare(p, gpu_run(L, p, 300, tile_w=tw, tile_h=th), oracle_run(p, 300),
+            F64_TOL, MASS_TOL)
+
+
+def test_results_do_not_depend_on_tiling(L):
+    """rho and u are bit-identical for every launch shape."""
+    p = cfg.cfg1("mls", "B")
+    ref = gpu_run(L, p, 200, tile_w=128, tile_h=16)
+    for tw, th in [(64, 16), (64, 5), (128, 128), (256, 3)]:
+        g = gpu_run(L, p, 200, tile_w=tw, tile_h=th)
+        for i in range(3):
+            assert np.array_equal(g[i], ref[i]), (tw, th, i)
+
+
+def test_tiny_domain_without_walls(L):
+    rng = np.random.default_rng(3)
+    n = 3
+    rho0 = 0.1 + 0.02 * rng.random((n, n))
+    p = cfg.free_droplet(n, 1.0).with_(rho0=rho0, name="tiny3")
+    compare(p, gpu_run(L, p, 50), oracle_run(p, 50), F64_TOL, MASS_TOL)
+
+
+def test_checkpoint_resume_is_bit_exact(L):
+    p = cfg.cfg1("mls", "A")
+    with L.Domain(p) as a:
+        a.step(37)
+        st = L.lbm_get_state(a.h)
+        a.step(25)
+        ra = a.moments()
+        ha = a.mass_history()
+    with L.Domain(p) as b:
+        L.lbm_set_state(b.h, st)
+        assert b.t == 37
+        b.step(25)
+        rb = b.moments()
+        hb = b.mass_history()
+    for i in range(3):
+        assert np.array_equal(ra[i], rb[i])
+    assert np.array_equal(ha, hb)
+
+
+def test_instability_is_reported_at_the_oracles_step(L):
+    p = cfg.cfg1("zhao_yong", "none")
+    o = ora.Oracle(p)
+    with pytest.raises(ora.OracleError):
+        o.step(200)
+    bad = o.t  # step index whose mass was not finite
+    with L.Domain(p) as d:
+        with pytest.raises(L.LbmError) as e:
+            d.step(200)
+        assert e.value.code == L.LBM_EUNSTABLE
+        assert L.lbm_unstable_step(d.h) == bad
+
+
+def test_long_run_mass_drift_fp64(L):
+    """Schemes A and B: |M(t) - M(0)| / M(0) <= 1e-10 over 1e5 steps."""
+    for fix in ("A", "B"):
+        p = cfg.cfg1("mls", fix)
+        with L.Domain(p, history_capacity=1 << 17) as d:
+            d.step(100000)
+            h = d.mass_history()
+        drift = np.max(np.abs(h - h[0])) / h[0]
+        say(f"    {fix}: max drift over 1e5 steps {drift:.3e}")
+        assert len(h) == 100001
+        assert drift <= 1e-10
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_full_size_2048_properties(L, storage):
+    """The 2048^2 MRT workload in the launch shape the benchmark times:
+    scheme B conserves mass to round-off (FP64), the mirror symmetry about
+    x = 1024 holds, and FP32 tracks FP64."""
+    p = cfg.cfg2a()
+    with L.Domain(p, storage=storage) as d:
+        d.step(300)
+        r, ux, uy = d.moments()
+        h = d.mass_history()
+        info = d.info()
+    say(f"    {storage} info {info}")
+    drift = np.max(np.abs(h - h[0])) / h[0]
+    say(f"    {storage} mass drift {drift:.3e}")
+    assert drift < (1e-13 if storage == "f64" else 1e-5)
+    mir = lambda a: np.roll(a[:, ::-1], 1, axis=1)
+    sym = np.max(np.abs(r - mir(r))) / r.max()
+    say(f"    {storage} mirror asymmetry {sym:.3e}")
+    assert sym < (1e-11 if storage == "f64" else 1e-5)
+    assert np.max(np.abs(ux + mir(ux))) < (1e-11 if storage == "f64" else 1e-5)
+    key = "full2048"
+    if storage == "f64":
+        _ORACLE[key] = (r, ux, uy)
+    elif key in _ORACLE:
+        fl = ~p.solid.astype(bool)
+        e = [rel_err((r, ux, uy)[i], _ORACLE[key][i], fl) for i in range(3)]
+        say(f"    fp32 vs fp64 {e}")
+        assert max(e) < 1e-4
