@@ -6,10 +6,11 @@ Carnahan-Starling EOS at 0.86 Tc, MRT with s_nu = 1/tau, tau = 0.8, MLS with
 scheme B, synthetic seeded geometry (no dataset).  One step = one pass of the
 whole hot path (boundary pass + fused stream/force/collide pass).
 
-Prints one JSON line: MLUPS over fluid nodes (whole job), the roofline of
-the main kernel (achieved HBM GB/s from its algorithmic bytes and its mean
-launch duration, timed with HIP events on its stream), the FP64 form of the
-same workload, and the CPU oracle timed on a bounded sample.
+Prints one JSON line: MLUPS over fluid nodes (whole job) of the plain form
+with FP32 populations (FP64 arithmetic), the roofline of the main kernel
+(achieved HBM GB/s from its algorithmic bytes and its mean launch duration,
+timed with HIP events on its stream), the FP64-storage and FP32-arithmetic
+forms of the same workload, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -22,7 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-BYTES_PER_POP = {"f64": 8, "f32": 4}
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f32_arith32": 4}
+ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32"}
 
 
 def source_hash():
@@ -91,9 +93,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--f64-steps", type=int, default=5000,
-                    help="steps of the FP64 form reported beside (0: skip)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f32_arith32"])
+    ap.add_argument("--other-steps", type=int, default=5000,
+                    help="steps of the other storage forms reported beside (0: skip)")
     ap.add_argument("--scale", type=float, default=16.0,
                     help="droplet geometry scale (16 = 2048 x 2048)")
     ap.add_argument("--tile-w", type=int, default=0)
@@ -134,19 +136,24 @@ def main():
     s = BYTES_PER_POP[a.storage]
     mlups = fluid * a.steps / r["seconds"] / 1e6
     alg_bytes = 18 * s * fluid  # 9 reads + 9 writes per fluid node
-    achieved = alg_bytes / (r["main_ms"] * 1e-3) / 1e9
+    achieved = alg_bytes / (r["main_ms"] * 1e-3) / 1e9 if r["main_ms"] > 0 else None
     traffic = traffic_record(a.storage, workload)
 
     also = {}
-    if a.f64_steps and a.storage != "f64":
-        r64 = run_gpu(p, "f64", a.f64_steps, a.warmup, stream, a.tile_w, a.tile_h,
-                      a.prof_every)
-        also["f64"] = {
-            "mlups": round(fluid * a.f64_steps / r64["seconds"] / 1e6, 1),
-            "ms_per_step": round(r64["seconds"] / a.f64_steps * 1e3, 5),
-            "main_kernel_ms": round(r64["main_ms"], 5),
-            "main_kernel_gbs": round(18 * 8 * fluid / (r64["main_ms"] * 1e-3) / 1e9, 1),
-            "mass_drift": r64["drift"], "steps": a.f64_steps}
+    for st in ("f64", "f32_arith32"):
+        if st == a.storage or a.other_steps <= 0:
+            continue
+        ro = run_gpu(p, st, a.other_steps, a.warmup, stream, a.tile_w, a.tile_h,
+                     a.prof_every)
+        so = BYTES_PER_POP[st]
+        also[st] = {
+            "storage": st, "arith": ARITH[st],
+            "mlups": round(fluid * a.other_steps / ro["seconds"] / 1e6, 1),
+            "ms_per_step": round(ro["seconds"] / a.other_steps * 1e3, 5),
+            "main_kernel_ms": round(ro["main_ms"], 5),
+            "main_kernel_gbs": (round(18 * so * fluid / (ro["main_ms"] * 1e-3) / 1e9, 1)
+                                if ro["main_ms"] > 0 else None),
+            "mass_drift": ro["drift"], "steps": a.other_steps}
 
     cpu = None
     if a.cpu_seconds > 0:
@@ -162,14 +169,15 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(r["seconds"] / a.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": a.storage, "data": "synthetic",
-        "config": {"workload": workload, "nx": p.nx, "ny": p.ny,
+        "dtype": ARITH[a.storage], "data": "synthetic",
+        "config": {"workload": workload, "storage": a.storage, "nx": p.nx, "ny": p.ny,
                    "fluid_nodes": fluid, "dense_mlups": round(n_dense * a.steps / r["seconds"] / 1e6, 1),
                    "collision": "mrt", "rule": "mls", "fix": "B", "eos": "cs@0.86Tc",
                    "tile_w": r["info"]["tile_w"], "tile_h": r["info"]["tile_h"],
                    "mass_drift": r["drift"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": achieved and round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved and round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
                      "kernel": "k_main", "kernel_ms": round(r["main_ms"], 5),
                      "kernel_samples": r["samples"],

@@ -80,9 +80,11 @@ enum lbm_eos {
 enum lbm_collision { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 
 enum lbm_storage {
-    LBM_STORE_F64 = 0,  /* FP64 populations, FP64 arithmetic               */
-    LBM_STORE_F32 = 1   /* FP32 populations, FP32 arithmetic; boundary
-                           sums and the total mass in FP64                 */
+    LBM_STORE_F64 = 0,         /* FP64 populations, FP64 arithmetic        */
+    LBM_STORE_F32 = 1,         /* FP32 populations, FP64 arithmetic        */
+    LBM_STORE_F32_ARITH32 = 2  /* FP32 populations, FP32 arithmetic (the
+                                  boundary rules, boundary sums and total
+                                  mass stay FP64 in every mode)           */
 };
 
 /* One cut link (40 bytes). */
@@ -96,7 +98,9 @@ typedef struct {
 } lbm_link;
 
 typedef struct {
-    int32_t nx, ny;            /* lattice size, each >= 3                   */
+    int32_t nx, ny;            /* lattice size, each >= 3; one buffer of
+                                  nine planes must stay below 4 GiB (about
+                                  59 M nodes in FP64, 119 M in FP32)      */
     const uint8_t *solid;      /* host, nx*ny, nonzero = solid node         */
     const lbm_link *links;     /* host, nlinks cut links                    */
     int64_t nlinks;

@@ -4,20 +4,21 @@
 // f*(t) in structure-of-arrays layout, nine planes of ny rows of `pitch`
 // elements.  A step is two launches:
 //
-//   k_boundary(cur): one thread per boundary node.  For each of the node's
-//     cut links it evaluates the wall rule (Eqs. 7-14) from f*(t) and the
-//     node's saved moments, then the leak of Eq. (15) and the correction of
-//     scheme A, B or Bao, and writes each incoming population into the
-//     solid neighbour's slot of the opposite direction (the "ghost" slot:
-//     the only slot a pull from the fluid node reads there).  Scheme A adds
-//     the leak to the node's own rest population.
+//   k_boundary(cur): one lane per cut link evaluates the wall rule
+//     (Eqs. 7-14) from f*(t) and the node's saved moments; the first lane
+//     of each boundary node then forms the node's sums for scheme B or Bao
+//     and the leak of Eq. (15) for scheme A.  Each incoming population is
+//     written into the solid neighbour's slot of the opposite direction
+//     (the "ghost" slot: the only slot a pull from the fluid node reads
+//     there).  Scheme A adds the leak to the node's own rest population.
 //
 //   k_main(cur -> nxt): pull-streaming (Eq. 3) of all nine populations,
 //     density, pseudopotential, the force of Eq. (16), the velocity of
 //     Eq. (5) and collision (Eq. 2), fused.  A workgroup owns a strip of
-//     tile_w columns and marches down tile_h rows, keeping psi of three
-//     consecutive rows in a four-slot LDS ring; the two halo columns of the
-//     strip are recomputed by two lanes.  Solid nodes are neither loaded nor
+//     tile_w columns and marches through tile_h rows, keeping psi of three
+//     consecutive rows in a four-slot LDS ring; the loads of the next two
+//     rows are in flight while a row is computed, and the first wavefront
+//     also pulls the strip's two halo columns.  Solid nodes are not
 //     stored.  Boundary nodes (and the x_f nodes that MLS reads) save their
 //     moments, and under Zhao-Yong their pre-collision populations, for the
 //     next k_boundary.  Each workgroup writes one FP64 partial of the total
@@ -32,9 +33,11 @@ constexpr int kMaxTileW = 256;
 
 enum : uint8_t { FL_SOLID = 1, FL_SAVE_MOM = 2, FL_SAVE_F = 4 };
 
-// wavefronts are handed to the 8 XCDs round robin; map consecutive
-// workgroup ids of one XCD to consecutive tiles (vertically adjacent
-// segments of a strip) so that they share that XCD's L2
+// Workgroups are handed to the 8 XCDs round robin.  Give XCD k a
+// contiguous run of tiles, numbered segment-major (all strips of a band of
+// rows), so that the workgroups that run together on one XCD cover a
+// compact block of the lattice and find each other's halo rows and columns
+// in that XCD's L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int xcd = b & 7, idx = b >> 3;
     const int q = nb >> 3, r = nb & 7;
@@ -54,167 +57,233 @@ struct MainArgs {
     double* __restrict__ mom_out;       // moments mode: rho, ux, uy planes
     int nx, ny, pitch;
     long long plane;                    // elements per population plane
-    int tile_h, nsegs;
+    int tile_h, nsegs, nstrips;
 };
 
-template <typename R, int EOS>
-struct NodeCtx {
-    const uint8_t* flags;
-    const R* psiw;
-    Phys<R> ph;
-};
+// Buffer resources: a 32-bit byte range on an SGPR base, so that a load
+// needs no per-lane address arithmetic (row offset in an SGPR, column
+// offset in a VGPR) and an access outside the range reads 0.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
 
-template <typename S, typename R>
-__device__ __forceinline__ void pull9(const S* __restrict__ src, long long plane,
-                                      int rm, int r0, int rp, int x, int xm,
-                                      int xp, R f[9]) {
-    // f_a(x, y) = f*_a(x - e_a, y): rows rm = y-1, r0 = y, rp = y+1
-    f[0] = R(src[0 * plane + r0 + x]);
-    f[1] = R(src[1 * plane + r0 + xm]);
-    f[2] = R(src[2 * plane + rm + x]);
-    f[3] = R(src[3 * plane + r0 + xp]);
-    f[4] = R(src[4 * plane + rp + x]);
-    f[5] = R(src[5 * plane + rm + xm]);
-    f[6] = R(src[6 * plane + rm + xp]);
-    f[7] = R(src[7 * plane + rp + xp]);
-    f[8] = R(src[8 * plane + rp + xm]);
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kRsrcWord3);
+}
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, unsigned v, unsigned s);
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+}
+template <>
+__device__ __forceinline__ uint8_t bload<uint8_t>(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, v, s, 0);
+}
+__device__ __forceinline__ void bstore(float x, rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+}
+__device__ __forceinline__ void bstore(double x, rsrc_t r, unsigned v, unsigned s) {
+    typedef __attribute__((ext_vector_type(2))) unsigned u2;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, v, s, 0);
 }
 
 template <typename R>
 __device__ __forceinline__ R dens(const R f[9]) {
-    return f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    return ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
 }
 
-// pull one node and return its psi (solid nodes: the wall value, no loads)
-template <typename S, typename R, int EOS>
-__device__ __forceinline__ R pull_psi(const MainArgs<S>& a, const R* psiw,
-                                      const Phys<R>& ph, int y, int x,
-                                      uint8_t& fl, R f[9]) {
-    const int ym = y == 0 ? a.ny - 1 : y - 1;
-    const int yp = y == a.ny - 1 ? 0 : y + 1;
-    const int xm = x == 0 ? a.nx - 1 : x - 1;
-    const int xp = x == a.nx - 1 ? 0 : x + 1;
-    const int r0 = y * a.pitch;
-    fl = a.flags[r0 + x];
-    if (fl & FL_SOLID) return psiw[r0 + x];
-    pull9<S, R>(a.src, a.plane, ym * a.pitch, r0, yp * a.pitch, x, xm, xp, f);
-    return psi_of<EOS, R>(dens<R>(f), ph);
-}
+// One row of a strip in flight, in the storage type: the pulled populations
+// of the thread's column and, in wave 0, of a halo column, with their flags
+// and (solid nodes) the wall psi.
+template <typename S, typename R>
+struct RowLoad {
+    S f[9];
+    S h[9];
+    R pw, hpw;
+    uint8_t fl, hfl;
+};
 
 // MOMENTS: write rho, u at every node instead of colliding and storing
-template <typename S, typename R, int EOS, int COLL, bool MOMENTS>
+template <typename S, typename R, int EOS, bool MOMENTS>
 __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
     __shared__ R ring[4][kMaxTileW + 2];
     __shared__ double wsum[kMaxTileW / 64];
-    const R* psiw = static_cast<const R*>(a.psiw);
+    constexpr unsigned ES = sizeof(S), RS = sizeof(R);
+    const unsigned pitch = (unsigned)a.pitch;
+    // one resource per buffer; plane and row offsets go in the scalar
+    // offset (the whole buffer is below 4 GiB)
+    const unsigned pb = (unsigned)(a.plane * ES);
+    const rsrc_t rs = make_rsrc(a.src, 9u * pb);
+    const rsrc_t rd = make_rsrc(a.dst, 9u * pb);
+    const rsrc_t rfl = make_rsrc(a.flags, pitch * (unsigned)a.ny);
+    const rsrc_t rpw = make_rsrc(a.psiw, pitch * (unsigned)a.ny * RS);
 
     const int tid = threadIdx.x;
     const int W = blockDim.x;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int strip = tile / a.nsegs, seg = tile - strip * a.nsegs;
+    const int seg = tile / a.nstrips, strip = tile - seg * a.nstrips;
     const int x0 = strip * W;
     const int ncols = min(W, a.nx - x0);
     const bool act = tid < ncols;
-    const int x = act ? x0 + tid : x0;
-    const bool halo = tid < 2;
-    const int hx = tid == 0 ? (x0 == 0 ? a.nx - 1 : x0 - 1)
-                            : (x0 + ncols == a.nx ? 0 : x0 + ncols);
-    const int hcol = tid == 0 ? 0 : ncols + 1;
+    const unsigned x = act ? x0 + tid : x0;
+    const unsigned xm = x == 0 ? a.nx - 1 : x - 1;
+    const unsigned xp = x == (unsigned)a.nx - 1 ? 0 : x + 1;
+    // wave 0 also pulls the two halo columns (even lanes left, odd right)
+    const bool hw = tid < 64;
+    const unsigned hxl = x0 == 0 ? a.nx - 1 : x0 - 1;
+    const unsigned hxr = x0 + ncols == a.nx ? 0 : x0 + ncols;
+    const unsigned hx = (tid & 1) ? hxr : hxl;
+    const unsigned hxm = hx == 0 ? a.nx - 1 : hx - 1;
+    const unsigned hxp = hx == (unsigned)a.nx - 1 ? 0 : hx + 1;
+    const int hcol = (tid & 1) ? ncols + 1 : 0;
+    // rows: even segments march up, odd ones down, so that neighbouring
+    // segments reach their shared boundary rows at the same time
     const int y0 = seg * a.tile_h;
-    const int y1 = min(y0 + a.tile_h, a.ny);
+    const int H = min(a.tile_h, a.ny - y0);
+    const int dir = (seg & 1) ? -1 : 1;
+    const int ystart = dir > 0 ? y0 : y0 + H - 1;
+    auto row_of = [&](int k) {
+        int y = ystart + dir * k;
+        return y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
+    };
 
-    R fc[9], fn[9], fh[9];
-    uint8_t flc = 0, fln = 0, flh = 0;
+    // flags of the next row to issue are loaded one issue ahead
+    uint8_t nfl, nhfl = 0;
+    auto load_flags = [&](int k) {
+        const unsigned r = (unsigned)row_of(k) * pitch;
+        nfl = bload<uint8_t>(rfl, x, r);
+        if (hw) nhfl = bload<uint8_t>(rfl, hx, r);
+    };
+    auto pull = [&](S f[9], R& pw, uint8_t fl, unsigned c, unsigned cm, unsigned cp,
+                    unsigned rm, unsigned r0, unsigned rp, unsigned prow) {
+        if (fl & FL_SOLID) {
+            pw = bload<R>(rpw, c * RS, prow);
+        } else {
+            f[0] = bload<S>(rs, c * ES, r0);
+            f[1] = bload<S>(rs, cm * ES, 1 * pb + r0);
+            f[2] = bload<S>(rs, c * ES, 2 * pb + rm);
+            f[3] = bload<S>(rs, cp * ES, 3 * pb + r0);
+            f[4] = bload<S>(rs, c * ES, 4 * pb + rp);
+            f[5] = bload<S>(rs, cm * ES, 5 * pb + rm);
+            f[6] = bload<S>(rs, cp * ES, 6 * pb + rm);
+            f[7] = bload<S>(rs, cp * ES, 7 * pb + rp);
+            f[8] = bload<S>(rs, cm * ES, 8 * pb + rp);
+        }
+    };
+    auto issue = [&](int k, RowLoad<S, R>& L) {
+        const int y = row_of(k);
+        L.fl = nfl;
+        L.hfl = nhfl;
+        load_flags(k + 1);
+        const unsigned r0 = (unsigned)y * pitch * ES;
+        const unsigned rm = (unsigned)(y == 0 ? a.ny - 1 : y - 1) * pitch * ES;
+        const unsigned rp = (unsigned)(y == a.ny - 1 ? 0 : y + 1) * pitch * ES;
+        const unsigned prow = (unsigned)y * pitch * RS;
+        pull(L.f, L.pw, L.fl, x, xm, xp, rm, r0, rp, prow);
+        if (hw) pull(L.h, L.hpw, L.hfl, hx, hxm, hxp, rm, r0, rp, prow);
+    };
+    auto psi_node = [&](const S fs[9], R pw, uint8_t fl) {
+        R f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = R(fs[q]);
+        return (fl & FL_SOLID) ? pw : psi_of<EOS, R>(dens<R>(f), ph);
+    };
+    auto publish = [&](const RowLoad<S, R>& L, int slot) {
+        if (act) ring[slot][tid + 1] = psi_node(L.f, L.pw, L.fl);
+        if (hw) {
+            const R hp = psi_node(L.h, L.hpw, L.hfl);
+            if (tid < 2) ring[slot][hcol] = hp;
+        }
+    };
+
     double msum = 0.0;
-
-    // prologue: psi of rows y0-1 (slot 0) and y0 (slot 1)
-    {
-        const int y = y0 == 0 ? a.ny - 1 : y0 - 1;
-        if (act) ring[0][tid + 1] = pull_psi<S, R, EOS>(a, psiw, ph, y, x, fln, fn);
-        if (halo) ring[0][hcol] = pull_psi<S, R, EOS>(a, psiw, ph, y, hx, flh, fh);
-        if (act) ring[1][tid + 1] = pull_psi<S, R, EOS>(a, psiw, ph, y0, x, flc, fc);
-        if (halo) ring[1][hcol] = pull_psi<S, R, EOS>(a, psiw, ph, y0, hx, flh, fh);
-    }
-
-    for (int k = 0, y = y0; y < y1; ++k, ++y) {
-        const int yn = y == a.ny - 1 ? 0 : y + 1;
+    // row k: collide with psi of rows k-1, k, k+1; then prefetch row k+3
+    auto step = [&](int k, RowLoad<S, R>& Lc, RowLoad<S, R>& Ln, RowLoad<S, R>& Lf) {
+        const int y = row_of(k);
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
-        if (act) ring[sp][tid + 1] = pull_psi<S, R, EOS>(a, psiw, ph, yn, x, fln, fn);
-        if (halo) ring[sp][hcol] = pull_psi<S, R, EOS>(a, psiw, ph, yn, hx, flh, fh);
+        const int sym = dir > 0 ? sm : sp, syp = dir > 0 ? sp : sm;
+        publish(Ln, sp);
         __syncthreads();
-        if (act && !(flc & FL_SOLID)) {
+        if (act && !(Lc.fl & FL_SOLID)) {
+            R fc[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fc[q] = R(Lc.f[q]);
             const int c = tid + 1;
             const R rho = dens<R>(fc);
+            const R irho = rcp(rho);
             R Fx = R(0), Fy = R(0);
             if constexpr (EOS != EOS_NONE) {
-                // Eq. (16): F = -G psi(x) sum_a w_a psi(x + e_a) e_a
-                const R p1 = ring[s0][c + 1], p2 = ring[sp][c], p3 = ring[s0][c - 1];
-                const R p4 = ring[sm][c], p5 = ring[sp][c + 1], p6 = ring[sp][c - 1];
-                const R p7 = ring[sm][c - 1], p8 = ring[sm][c + 1];
+                // Eq. (16): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, with
+                // opposite neighbours paired
+                const R p1 = ring[s0][c + 1], p3 = ring[s0][c - 1];
+                const R p2 = ring[syp][c], p4 = ring[sym][c];
+                const R p5 = ring[syp][c + 1], p6 = ring[syp][c - 1];
+                const R p7 = ring[sym][c - 1], p8 = ring[sym][c + 1];
                 const R w1 = R(wf(1)), w5 = R(wf(5));
-                R sx, sy;
-                if constexpr (sizeof(R) == 8) {
-                    // the sum in direction order
-                    sx = w1 * p1 - w1 * p3 + w5 * p5 - w5 * p6 - w5 * p7 + w5 * p8;
-                    sy = w1 * p2 - w1 * p4 + w5 * p5 + w5 * p6 - w5 * p7 - w5 * p8;
-                } else {
-                    // opposite neighbours paired first: exactly zero where psi
-                    // is uniform and exactly odd under reflection, also when
-                    // products fuse into multiply-adds
-                    sx = w1 * (p1 - p3) + w5 * ((p5 - p7) + (p8 - p6));
-                    sy = w1 * (p2 - p4) + w5 * ((p5 - p7) + (p6 - p8));
-                }
-                const R pc = ring[s0][c];
-                Fx = -ph.G * pc * sx;
-                Fy = -ph.G * pc * sy;
+                const R sx = w1 * (p1 - p3) + w5 * ((p5 - p7) + (p8 - p6));
+                const R sy = w1 * (p2 - p4) + w5 * ((p5 - p7) + (p6 - p8));
+                const R g = -ph.G * ring[s0][c];
+                Fx = g * sx;
+                Fy = g * sy;
             }
-            Fx = Fx + rho * ph.gx;
-            Fy = Fy + rho * ph.gy;
+            Fx += rho * ph.gx;
+            Fy += rho * ph.gy;
             // Eq. (5)
-            const R mx = fc[1] - fc[3] + fc[5] - fc[6] - fc[7] + fc[8];
-            const R my = fc[2] - fc[4] + fc[5] + fc[6] - fc[7] - fc[8];
-            const R ux = (mx + Fx / R(2)) / rho;
-            const R uy = (my + Fy / R(2)) / rho;
-            const int idx = y * a.pitch + x;
+            const R mx = (fc[1] - fc[3]) + ((fc[5] - fc[7]) + (fc[8] - fc[6]));
+            const R my = (fc[2] - fc[4]) + ((fc[5] - fc[7]) + (fc[6] - fc[8]));
+            const R ux = (mx + R(0.5) * Fx) * irho;
+            const R uy = (my + R(0.5) * Fy) * irho;
             if constexpr (MOMENTS) {
-                const int o = y * a.nx + x;
+                const long long o = (long long)y * a.nx + x;
+                const long long n2 = (long long)a.nx * a.ny;
                 a.mom_out[o] = double(rho);
-                a.mom_out[(long long)a.nx * a.ny + o] = double(ux);
-                a.mom_out[2LL * a.nx * a.ny + o] = double(uy);
+                a.mom_out[n2 + o] = double(ux);
+                a.mom_out[2 * n2 + o] = double(uy);
             } else {
-                if (sizeof(R) == 8) {
-                    msum += double(rho);
-                } else {
-                    double r = 0.0;
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) r += double(fc[q]);
-                    msum += r;
-                }
-                if (flc & (FL_SAVE_MOM | FL_SAVE_F)) {
-                    const int slot = a.side_idx[idx];
-                    if (flc & FL_SAVE_MOM) {
+                msum += double(rho);
+                if (Lc.fl & (FL_SAVE_MOM | FL_SAVE_F)) {
+                    const int slot = a.side_idx[(unsigned)y * pitch + x];
+                    if (Lc.fl & FL_SAVE_MOM) {
                         a.side_mom[3 * slot + 0] = double(rho);
                         a.side_mom[3 * slot + 1] = double(ux);
                         a.side_mom[3 * slot + 2] = double(uy);
                     }
-                    if (flc & FL_SAVE_F) {
+                    if (Lc.fl & FL_SAVE_F) {
 #pragma unroll
                         for (int q = 0; q < 9; ++q) a.side_f[9 * slot + q] = double(fc[q]);
                     }
                 }
-                collide<COLL, R>(fc, rho, ux, uy, Fx, Fy, ph);
+                collide<R>(fc, rho, ux, uy, Fx, Fy, ph);
+                const unsigned r0 = (unsigned)y * pitch * ES;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) a.dst[q * a.plane + idx] = S(fc[q]);
+                for (int q = 0; q < 9; ++q) bstore(S(fc[q]), rd, x * ES, q * pb + r0);
             }
         } else if (MOMENTS && act) {
-            const int o = y * a.nx + x;
+            const long long o = (long long)y * a.nx + x;
+            const long long n2 = (long long)a.nx * a.ny;
             a.mom_out[o] = 0.0;
-            a.mom_out[(long long)a.nx * a.ny + o] = 0.0;
-            a.mom_out[2LL * a.nx * a.ny + o] = 0.0;
+            a.mom_out[n2 + o] = 0.0;
+            a.mom_out[2 * n2 + o] = 0.0;
         }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) fc[q] = fn[q];
-        flc = fln;
+        if (k + 3 <= H) issue(k + 3, Lc);  // Lc is free again
+    };
+
+    RowLoad<S, R> A, B, C;
+    load_flags(-1);
+    issue(-1, C);
+    publish(C, 0);
+    issue(0, A);
+    issue(1, B);
+    publish(A, 1);
+    if (H > 1) issue(2, C);
+    for (int k = 0; k < H; k += 3) {
+        step(k, A, B, C);
+        if (k + 1 < H) step(k + 1, B, C, A);
+        if (k + 2 < H) step(k + 2, C, A, B);
     }
 
     if constexpr (!MOMENTS) {
@@ -273,19 +342,21 @@ enum : int {
     LK_ZY = 8        // c1 f*_abar(x_b) + c2 f_a(x_b)
 };
 
+// One lane per cut link.  Links are grouped by boundary node (directions
+// ascending) and the groups are padded so that none straddles a
+// workgroup; per-node sums are taken by the group's first lane from LDS in
+// link order.
 struct BndArgs {
-    int nb;                          // boundary nodes
-    const int* __restrict__ bnode;   // node index (pitch layout)
-    const int* __restrict__ bslot;   // side slot of the node
-    const int* __restrict__ bstart;  // CSR into links, nb + 1
-    const int* __restrict__ ldir;
-    const int* __restrict__ lkind;
-    const int* __restrict__ lghost;  // node index of x_s
-    const int* __restrict__ lxf;     // node index of x_f (or -1)
-    const int* __restrict__ lxff;    // node index of x_ff (or -1)
+    int nslot;                       // link slots, padding included
+    const int* __restrict__ lnode;   // x_b (pitch layout)
+    const int* __restrict__ lmeta;   // dir | kind << 4 | len << 8 | pos << 12
+    const int* __restrict__ lghost;  // solid neighbour x_s
+    const int* __restrict__ lxf;     // x_f (or -1)
+    const int* __restrict__ lxff;    // x_ff (or -1)
+    const int* __restrict__ lslotb;  // side slot of x_b
     const int* __restrict__ lslotf;  // side slot of x_f (or -1)
-    const double* __restrict__ lc;   // [link][8]: c1 c2 c3 chi cb uwq_x uwq_y pad
-    const double* __restrict__ luw;  // [link][2]: wall velocity
+    const double* __restrict__ lc;   // [slot][8]: c1 c2 c3 chi cb uwq_x uwq_y pad
+    const double* __restrict__ luw;  // [slot][2]: wall velocity
     const double* __restrict__ side_mom;
     const double* __restrict__ side_f;
     long long plane;
@@ -299,105 +370,117 @@ struct BndArgs {
     int do_reduce;
 };
 
+constexpr int LK_PAD = 15;
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
     if (blockIdx.x == gridDim.x - 1) {
         if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
         return;
     }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= b.nb) return;
-    const int node = b.bnode[i];
-    const int k0 = b.bstart[i], k1 = b.bstart[i + 1];
-    const double* mom = b.side_mom + 3 * b.bslot[i];
-    const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
+    __shared__ double s_fab[256], s_inc[256], s_chi[256], s_br[256], s_wall[256];
+    __shared__ double s_rhos[256];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * 256 + tid;
+    const int meta = i < b.nslot ? b.lmeta[i] : (LK_PAD << 4);
+    const int d = meta & 15, kind = (meta >> 4) & 15;
+    const int len = (meta >> 8) & 15, pos = (meta >> 12) & 15;
+    const bool active = kind != LK_PAD;
     const long long P = b.plane;
-
-    double inc[8], fab[8], chi[8], br[8], wall[8];
-    int n = 0;
-    for (int k = k0; k < k1; ++k, ++n) {
-        const int d = b.ldir[k];
+    int node = 0;
+    double fab = 0.0, r = 0.0, ch = 0.0, bk = 0.0, wl = 0.0;
+    if (active) {
+        node = b.lnode[i];
         const int od = opp(d);
-        const double* c = b.lc + 8 * k;
+        const double* c = b.lc + 8 * i;
+        const double* mom = b.side_mom + 3 * b.lslotb[i];
+        const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
         const double ex = double(cx(d)), ey = double(cy(d));
-        const double fa_b = double(A[d * P + node]);
-        const double uwx = b.luw[2 * k], uwy = b.luw[2 * k + 1];
+        fab = double(A[d * P + node]);
+        const double uwx = b.luw[2 * i], uwy = b.luw[2 * i + 1];
         // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
-        const double wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
-        double r = 0.0, ch = 0.0, bk = 0.0;
-        const int kind = b.lkind[k];
+        wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
         if (kind == LK_HALFWAY) {
-            r = fa_b - wl;
+            r = fab - wl;
         } else if (kind <= LK_CHI_EXT) {
             double usx, usy;
             if (kind == LK_CHI_UB) {
-                usx = ubx; usy = uby;
+                usx = ubx;
+                usy = uby;
             } else if (kind == LK_CHI_UF) {
-                const double* mf = b.side_mom + 3 * b.lslotf[k];
-                usx = mf[1]; usy = mf[2];
+                const double* mf = b.side_mom + 3 * b.lslotf[i];
+                usx = mf[1];
+                usy = mf[2];
             } else {
                 usx = c[4] * ubx + c[5];
                 usy = c[4] * uby + c[6];
             }
             ch = c[3];
+            // Eq. (8): w_a [1 + 3 e.u_s + 4.5 (e.u_b)^2 - 1.5 u_b^2]
             const double eus = edot<double>(d, usx, usy);
             const double eub = edot<double>(d, ubx, uby);
             const double ub2 = ubx * ubx + uby * uby;
             bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
-            r = (1.0 - ch) * fa_b + ch * (rho_b * bk) - wl;
+            r = (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
         } else if (kind == LK_LIN_F) {
-            r = c[0] * fa_b + c[1] * double(A[d * P + b.lxf[k]]);
+            r = c[0] * fab + c[1] * double(A[d * P + b.lxf[i]]);
         } else if (kind == LK_LIN_B) {
-            r = c[0] * fa_b + c[1] * double(A[od * P + node]);
+            r = c[0] * fab + c[1] * double(A[od * P + node]);
         } else if (kind == LK_QUAD_F) {
-            r = c[0] * fa_b + c[1] * double(A[d * P + b.lxf[k]]) -
-                c[2] * double(A[d * P + b.lxff[k]]);
+            r = c[0] * fab + c[1] * double(A[d * P + b.lxf[i]]) -
+                c[2] * double(A[d * P + b.lxff[i]]);
         } else if (kind == LK_QUAD_B) {
-            r = c[0] * fa_b + c[1] * double(A[od * P + node]) -
-                c[2] * double(A[od * P + b.lxf[k]]);
-        } else {  // LK_ZY
-            const double fpre = b.side_f[9 * b.bslot[i] + d];
-            r = c[0] * double(A[od * P + node]) + c[1] * fpre;
+            r = c[0] * fab + c[1] * double(A[od * P + node]) -
+                c[2] * double(A[od * P + b.lxf[i]]);
+        } else {  // LK_ZY, Eq. (14)
+            r = c[0] * double(A[od * P + node]) + c[1] * b.side_f[9 * b.lslotb[i] + d];
         }
-        inc[n] = r;
-        fab[n] = fa_b;
-        chi[n] = ch;
-        br[n] = bk;
-        wall[n] = wl;
     }
+    s_fab[tid] = fab;
+    s_inc[tid] = r;
+    s_chi[tid] = ch;
+    s_br[tid] = bk;
+    s_wall[tid] = wl;
+    __syncthreads();
+    const bool head = active && pos == 0;
+    const int h = tid - pos;
     if (b.fix == 2 || b.fix == 3) {
         // scheme B, Eq. 22 (chi inside the sums) or Bao et al., Eq. 23
-        double num = 0.0, den = 0.0, mag = 0.0;
-        for (int m = 0; m < n; ++m) {
-            if (b.fix == 2) {
-                num += chi[m] * fab[m];
-                den += chi[m] * br[m];
-                mag += fabs(chi[m] * br[m]);
-            } else {
-                num += fab[m];
-                den += br[m];
-                mag += fabs(br[m]);
+        if (head) {
+            double num = 0.0, den = 0.0, mag = 0.0;
+            for (int m = 0; m < len; ++m) {
+                if (b.fix == 2) {
+                    num += s_chi[tid + m] * s_fab[tid + m];
+                    den += s_chi[tid + m] * s_br[tid + m];
+                    mag += fabs(s_chi[tid + m] * s_br[tid + m]);
+                } else {
+                    num += s_fab[tid + m];
+                    den += s_br[tid + m];
+                    mag += fabs(s_br[tid + m]);
+                }
+            }
+            s_rhos[tid] = (den != 0.0 && fabs(den) > 1e-12 * mag) ? num / den : NAN;
+        }
+        __syncthreads();
+        if (active) {
+            const double rho_s = s_rhos[h];
+            if (!isnan(rho_s)) {
+                r = (1.0 - ch) * fab + ch * (rho_s * bk) - wl;
+                s_inc[tid] = r;
             }
         }
-        if (den != 0.0 && fabs(den) > 1e-12 * mag) {
-            const double rho_s = num / den;
-            for (int m = 0; m < n; ++m)
-                inc[m] = (1.0 - chi[m]) * fab[m] + chi[m] * (rho_s * br[m]) - wall[m];
+        __syncthreads();
+    }
+    if (active) A[opp(d) * P + b.lghost[i]] = S(r);
+    if (head && b.fix == 1) {
+        // Eq. (15) without the wall momentum, added to the rest population
+        // (Eq. 18)
+        double out_sum = 0.0, in_sum = 0.0;
+        for (int m = 0; m < len; ++m) {
+            out_sum += s_fab[tid + m];
+            in_sum += s_inc[tid + m] + s_wall[tid + m];
         }
-    }
-    // Eq. (15) without the wall momentum, written back as incoming values
-    double out_sum = 0.0, in_sum = 0.0;
-    n = 0;
-    for (int k = k0; k < k1; ++k, ++n) {
-        const int d = b.ldir[k];
-        out_sum += fab[n];
-        in_sum += inc[n] + wall[n];
-        A[opp(d) * P + b.lghost[k]] = S(inc[n]);
-    }
-    if (b.fix == 1) {
-        // Eq. (18)
-        const double f0 = double(A[node]);
-        A[node] = S(f0 + (out_sum - in_sum));
+        A[node] = S(double(A[node]) + (out_sum - in_sum));
     }
 }
 

@@ -2,9 +2,6 @@
 // the device.  Directions: 0 rest, 1 (+1,0), 2 (0,+1), 3 (-1,0), 4 (0,-1),
 // 5 (+1,+1), 6 (-1,+1), 7 (-1,-1), 8 (+1,-1).
 //
-// Products with the lattice velocity components (0, +1, -1) are written as
-// the signed sums they are, so that each expression rounds exactly as the
-// textbook formula evaluated left to right.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,142 +47,110 @@ __host__ __device__ __forceinline__ R edot(int a, R vx, R vy) {
 template <typename R>
 struct Phys {
     R G, gx, gy;
-    R omega;       // 1/tau
-    R guo_pref;    // 1 - 1/(2 tau)
     R e0, e1, e2, e3;  // EOS parameters
-    R s[9];        // MRT rates
+    R p2G;             // 2 / G
+    R s[9];        // relaxation rates of the nine moments (BGK: all 1/tau)
 };
 
 enum { EOS_NONE = 0, EOS_EXP = 1, EOS_CS = 2 };
-enum { COLL_BGK = 0, COLL_MRT = 1 };
+
+// Reciprocal and square root: correctly rounded in FP64; the hardware
+// instructions (1 ulp) in FP32.
+__host__ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ double root(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ float root(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
 
 // Pseudopotential.  EXP: psi0 exp(-rho0/rho).  CS: sqrt(2 (p - rho/3)/G)
-// with p the Carnahan-Starling pressure.
+// with p the Carnahan-Starling pressure.  p2G = 2/G.
 template <int EOS, typename R>
 __host__ __device__ __forceinline__ R psi_of(R rho, const Phys<R>& p) {
     if constexpr (EOS == EOS_EXP) {
-        return p.e0 * exp(-p.e1 / rho);
+        return p.e0 * exp(-p.e1 * rcp(rho));
     } else if constexpr (EOS == EOS_CS) {
         const R a = p.e0, b = p.e1, Rg = p.e2, T = p.e3;
-        const R eta = b * rho / R(4);
-        const R num = R(1) + eta + eta * eta - eta * eta * eta;
-        const R den = (R(1) - eta) * (R(1) - eta) * (R(1) - eta);
-        const R pe = rho * Rg * T * num / den - a * rho * rho;
-        const R v = R(2) * (pe - rho * R(1.0 / 3.0)) / p.G;
-        return sqrt(v);
+        const R eta = R(0.25) * b * rho;
+        const R num = R(1) + eta * (R(1) + eta * (R(1) - eta));
+        const R om = R(1) - eta;
+        const R den = om * om * om;
+        const R pe = (rho * Rg * T) * num * rcp(den) - a * rho * rho;
+        return root(p.p2G * (pe - rho * R(1.0 / 3.0)));
     } else {
         return R(0);
     }
 }
 
-// Equilibrium, Eq. (4): w rho (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u)
+// Collision, Eq. (2), with Guo forcing, in the D2Q9 moment space of
+// Lallemand & Luo (rows rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy):
+//   m* = m + S (m_eq - m) + (I - S/2) M Fbar,   f* = f + M^-1 (m* - m).
+// BGK is the case of equal rates 1/tau.  The equilibrium moments of Eq. (4)
+// and the moments of the Guo source are written in closed form:
+//   e_eq = -2 rho + 3 rho u^2, eps_eq = rho - 3 rho u^2, j = rho u,
+//   q_eq = -rho u, p_xx,eq = rho (ux^2 - uy^2), p_xy,eq = rho ux uy;
+//   (M Fbar) = (0, 6 u.F, -6 u.F, Fx, -Fx, Fy, -Fy, 2 (ux Fx - uy Fy),
+//               ux Fy + uy Fx).
+// With j_eq - j = F/2 (Eq. 5) the momentum moments change by exactly F.
+// The update is formed as increments of the populations, opposite
+// directions paired, and the rest increment closes the mass balance, so
+// the arithmetic acts on the small non-equilibrium parts and each
+// expression is exactly symmetric under lattice reflections.
 template <typename R>
-__device__ __forceinline__ R feq_a(int a, R rho, R ux, R uy, R usq) {
-    const R eu = edot<R>(a, ux, uy);
-    return R(wt(a)) * rho * (R(1) + R(3) * eu + R(4.5) * (eu * eu) - R(1.5) * usq);
-}
-
-// Guo source without its prefactor: w [3 (e - u) + 9 (e.u) e] . F
-template <typename R>
-__device__ __forceinline__ R guo_raw_a(int a, R ux, R uy, R Fx, R Fy) {
-    const R eu = edot<R>(a, ux, uy);
-    R gx = R(3) * (R(cx(a)) - ux);
-    R gy = R(3) * (R(cy(a)) - uy);
-    if (cx(a) == 1) gx = gx + R(9) * eu;
-    if (cx(a) == -1) gx = gx + -(R(9) * eu);
-    if (cy(a) == 1) gy = gy + R(9) * eu;
-    if (cy(a) == -1) gy = gy + -(R(9) * eu);
-    return gx * Fx + gy * Fy;
-}
-
-// Lallemand-Luo D2Q9 moment basis: integer matrix entries.
-__host__ __device__ constexpr int mrt_m(int i, int a) {
-    // rows: rho, e, eps, jx, qx, jy, qy, pxx, pxy
-    return i == 0 ? 1
-         : i == 1 ? (a == 0 ? -4 : (a <= 4 ? -1 : 2))
-         : i == 2 ? (a == 0 ? 4 : (a <= 4 ? -2 : 1))
-         : i == 3 ? cx(a)
-         : i == 4 ? (a == 0 ? 0 : (a <= 4 ? -2 * cx(a) : cx(a)))
-         : i == 5 ? cy(a)
-         : i == 6 ? (a == 0 ? 0 : (a <= 4 ? -2 * cy(a) : cy(a)))
-         : i == 7 ? cx(a) * cx(a) - cy(a) * cy(a)
-         : cx(a) * cy(a);
-}
-__host__ __device__ constexpr int mrt_norm2(int i) {
-    return i == 0 ? 9 : i == 1 ? 36 : i == 2 ? 36 : i == 3 ? 6 : i == 4 ? 12
-         : i == 5 ? 6 : i == 6 ? 12 : 4;
-}
-
-// y = M x, summed in direction order (zero entries skipped: adding a signed
-// zero never changes a sum)
-template <typename R>
-__device__ __forceinline__ void mrt_fwd(const R x[9], R y[9]) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        R acc = R(0);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const int m = mrt_m(i, a);
-            if (m == 1) acc = acc + x[a];
-            else if (m == -1) acc = acc + -x[a];
-            else if (m != 0) acc = acc + R(m) * x[a];
-        }
-        y[i] = acc;
-    }
-}
-
-// x = M^-1 y with M^-1 = M^T diag(1/|row|^2)
-template <typename R>
-__device__ __forceinline__ void mrt_inv(const R y[9], R x[9]) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        R acc = R(0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const int m = mrt_m(i, a);
-            if (m != 0) acc = acc + R(double(m) / double(mrt_norm2(i))) * y[i];
-        }
-        x[a] = acc;
-    }
-}
-
-// Collision, Eq. (2), with Guo forcing.  f is overwritten by f*.
-//
-// In FP32 the rounded lattice weights sum to 1 + 7e-9, so the textbook form
-// would create that much mass at every collision; there the rest population
-// is taken from mass conservation instead, f*_0 = rho - sum_{a>0} f*_a,
-// which is the same value in exact arithmetic.
-template <int COLL, typename R>
 __device__ __forceinline__ void collide(R f[9], R rho, R ux, R uy, R Fx, R Fy,
                                         const Phys<R>& p) {
-    constexpr bool kMassExact = sizeof(R) == 4;
-    const R usq = ux * ux + uy * uy;
-    if constexpr (COLL == COLL_BGK) {
-#pragma unroll
-        for (int a = kMassExact ? 1 : 0; a < 9; ++a) {
-            const R feq = feq_a<R>(a, rho, ux, uy, usq);
-            const R guo = p.guo_pref * R(wt(a)) * guo_raw_a<R>(a, ux, uy, Fx, Fy);
-            f[a] = f[a] - p.omega * (f[a] - feq) + guo;
-        }
-        if constexpr (kMassExact)
-            f[0] = rho - (f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
-    } else {
-        R feq[9], fb[9], m[9], meq[9], mf[9], ms[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            feq[a] = feq_a<R>(a, rho, ux, uy, usq);
-            fb[a] = R(wt(a)) * guo_raw_a<R>(a, ux, uy, Fx, Fy);
-        }
-        mrt_fwd<R>(f, m);
-        mrt_fwd<R>(feq, meq);
-        mrt_fwd<R>(fb, mf);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            ms[i] = m[i] - p.s[i] * (m[i] - meq[i]) + (R(1) - p.s[i] / R(2)) * mf[i];
-        mrt_inv<R>(ms, f);
-        if constexpr (kMassExact)
-            f[0] = rho - (f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]);
-    }
+    const R s1 = f[1] + f[3], s2 = f[2] + f[4], c1 = f[5] + f[7], c2 = f[6] + f[8];
+    const R d1 = f[1] - f[3], d2 = f[2] - f[4], e1 = f[5] - f[7], e2 = f[6] - f[8];
+    const R sa = s1 + s2, sd = c1 + c2;
+    const R m_e = (sd + sd) - sa - R(4) * f[0];
+    const R m_p = R(4) * f[0] - (sa + sa) + sd;
+    const R m_qx = (e1 - e2) - (d1 + d1);
+    const R m_qy = (e1 + e2) - (d2 + d2);
+    const R m_xx = s1 - s2, m_xy = c1 - c2;
+    const R uxx = ux * ux, uyy = uy * uy, usq = uxx + uyy;
+    const R uF = ux * Fx + uy * Fy;
+    const R ru2 = R(3) * rho * usq;
+    const R De = p.s[1] * ((ru2 - (rho + rho)) - m_e) + (R(1) - R(0.5) * p.s[1]) * (R(6) * uF);
+    const R Dp = p.s[2] * ((rho - ru2) - m_p) - (R(1) - R(0.5) * p.s[2]) * (R(6) * uF);
+    const R Dqx = -p.s[4] * (rho * ux + m_qx) - (R(1) - R(0.5) * p.s[4]) * Fx;
+    const R Dqy = -p.s[6] * (rho * uy + m_qy) - (R(1) - R(0.5) * p.s[6]) * Fy;
+    const R Dxx = p.s[7] * (rho * (uxx - uyy) - m_xx) +
+                  (R(1) - R(0.5) * p.s[7]) * (R(2) * (ux * Fx - uy * Fy));
+    const R Dxy = p.s[8] * (rho * (ux * uy) - m_xy) +
+                  (R(1) - R(0.5) * p.s[8]) * (ux * Fy + uy * Fx);
+    // M^-1 = M^T diag(1/|row|^2), |row|^2 = 9, 36, 36, 6, 12, 6, 12, 4, 4
+    const R ke = De * R(1.0 / 36.0), kp = Dp * R(1.0 / 36.0);
+    const R kjx = Fx * R(1.0 / 6.0), kjy = Fy * R(1.0 / 6.0);
+    const R kqx = Dqx * R(1.0 / 12.0), kqy = Dqy * R(1.0 / 12.0);
+    const R kxx = Dxx * R(0.25), kxy = Dxy * R(0.25);
+    const R A = -ke - (kp + kp), B = (ke + ke) + kp;
+    const R X = kjx - (kqx + kqx), Y = kjy - (kqy + kqy);
+    const R P = kjx + kqx, Q = kjy + kqy;
+    const R g1 = (A + kxx) + X, g3 = (A + kxx) - X;
+    const R g2 = (A - kxx) + Y, g4 = (A - kxx) - Y;
+    const R bp = B + kxy, bm = B - kxy;
+    const R g5 = bp + (P + Q), g7 = bp - (P + Q);
+    const R g6 = bm + (Q - P), g8 = bm - (Q - P);
+    const R g0 = -(((g1 + g3) + (g2 + g4)) + ((g5 + g7) + (g6 + g8)));
+    f[0] += g0;
+    f[1] += g1;
+    f[2] += g2;
+    f[3] += g3;
+    f[4] += g4;
+    f[5] += g5;
+    f[6] += g6;
+    f[7] += g7;
+    f[8] += g8;
 }
 
 }  // namespace lbm

@@ -12,8 +12,9 @@ namespace lbm {
 struct Ctx {
     int nx, ny, pitch;
     long long plane;
-    int eos, coll;
-    int tile_w, tile_h, nsegs, nblocks;
+    int eos;
+    int storage;  // lbm_storage
+    int tile_w, tile_h, nsegs, nstrips, nblocks;
     const uint8_t* flags;
     void* psiw;
     const int* side_idx;

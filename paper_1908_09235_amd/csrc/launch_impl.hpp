@@ -11,17 +11,16 @@ Phys<R> convert(const Phys<double>& d) {
     p.G = R(d.G);
     p.gx = R(d.gx);
     p.gy = R(d.gy);
-    p.omega = R(d.omega);
-    p.guo_pref = R(d.guo_pref);
     p.e0 = R(d.e0);
     p.e1 = R(d.e1);
     p.e2 = R(d.e2);
     p.e3 = R(d.e3);
+    p.p2G = R(d.p2G);
     for (int i = 0; i < 9; ++i) p.s[i] = R(d.s[i]);
     return p;
 }
 
-template <typename S, typename R, int EOS, int COLL, bool MOM>
+template <typename S, typename R, int EOS, bool MOM>
 void main_t(const Ctx& c, const S* src, S* dst) {
     MainArgs<S> a{};
     a.src = src;
@@ -39,7 +38,8 @@ void main_t(const Ctx& c, const S* src, S* dst) {
     a.plane = c.plane;
     a.tile_h = c.tile_h;
     a.nsegs = c.nsegs;
-    hipLaunchKernelGGL((k_main<S, R, EOS, COLL, MOM>), dim3(c.nblocks), dim3(c.tile_w), 0,
+    a.nstrips = c.nstrips;
+    hipLaunchKernelGGL((k_main<S, R, EOS, MOM>), dim3(c.nblocks), dim3(c.tile_w), 0,
                        c.stream, a, convert<R>(c.ph));
 }
 
@@ -47,15 +47,9 @@ template <typename S, typename R, bool MOM>
 void main_s(const Ctx& c, const void* src, void* dst) {
     const S* s = static_cast<const S*>(src);
     S* t = static_cast<S*>(dst);
-    if (c.coll == COLL_BGK) {
-        if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, COLL_BGK, MOM>(c, s, t);
-        else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, COLL_BGK, MOM>(c, s, t);
-        else main_t<S, R, EOS_CS, COLL_BGK, MOM>(c, s, t);
-    } else {
-        if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, COLL_MRT, MOM>(c, s, t);
-        else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, COLL_MRT, MOM>(c, s, t);
-        else main_t<S, R, EOS_CS, COLL_MRT, MOM>(c, s, t);
-    }
+    if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, MOM>(c, s, t);
+    else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, MOM>(c, s, t);
+    else main_t<S, R, EOS_CS, MOM>(c, s, t);
 }
 
 template <typename S, typename R>

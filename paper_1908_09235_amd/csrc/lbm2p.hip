@@ -41,9 +41,9 @@ struct lbm_domain {
     long long* unstable = nullptr;
     double* mom_out = nullptr;
     int nb = 0, nl = 0;
-    int *bnode = nullptr, *bslot = nullptr, *bstart = nullptr, *ldir = nullptr,
-        *lkind = nullptr, *lghost = nullptr, *lxf = nullptr, *lxff = nullptr,
-        *lslotf = nullptr;
+    int nslot_links = 0;
+    int *lnode = nullptr, *lmeta = nullptr, *lghost = nullptr, *lxf = nullptr,
+        *lxff = nullptr, *lslotb = nullptr, *lslotf = nullptr;
     double *lc = nullptr, *luw = nullptr;
     long long cap = 0, t = 0;
     bool pending = false;
@@ -99,13 +99,14 @@ Phys<R> make_phys(const lbm_desc* s) {
     p.G = R(s->G);
     p.gx = R(s->gravity[0]);
     p.gy = R(s->gravity[1]);
-    p.omega = R(1.0 / s->tau);
-    p.guo_pref = R(1.0 - 1.0 / (2.0 * s->tau));
     p.e0 = R(s->eos_param[0]);
     p.e1 = R(s->eos_param[1]);
     p.e2 = R(s->eos_param[2]);
     p.e3 = R(s->eos_param[3]);
-    for (int i = 0; i < 9; ++i) p.s[i] = R(s->mrt_s[i]);
+    p.p2G = R(s->G != 0.0 ? 2.0 / s->G : 0.0);
+    // BGK is the moment-space collision with every rate 1/tau
+    for (int i = 0; i < 9; ++i)
+        p.s[i] = R(s->collision == LBM_COLL_MRT ? s->mrt_s[i] : 1.0 / s->tau);
     return p;
 }
 
@@ -123,10 +124,11 @@ Ctx ctx(lbm_domain* d) {
     c.pitch = d->pitch;
     c.plane = d->plane;
     c.eos = d->eos;
-    c.coll = d->coll;
+    c.storage = d->storage;
     c.tile_w = d->tile_w;
     c.tile_h = d->tile_h;
     c.nsegs = d->nsegs;
+    c.nstrips = d->nstrips;
     c.nblocks = d->nblocks;
     c.flags = d->flags;
     c.psiw = d->psiw;
@@ -147,15 +149,13 @@ void launch_main(lbm_domain* d, const void* src, void* dst, bool moments) {
 
 BndArgs bnd_args(lbm_domain* d) {
     BndArgs b{};
-    b.nb = d->nb;
-    b.bnode = d->bnode;
-    b.bslot = d->bslot;
-    b.bstart = d->bstart;
-    b.ldir = d->ldir;
-    b.lkind = d->lkind;
+    b.nslot = d->nslot_links;
+    b.lnode = d->lnode;
+    b.lmeta = d->lmeta;
     b.lghost = d->lghost;
     b.lxf = d->lxf;
     b.lxff = d->lxff;
+    b.lslotb = d->lslotb;
     b.lslotf = d->lslotf;
     b.lc = d->lc;
     b.luw = d->luw;
@@ -175,7 +175,7 @@ BndArgs bnd_args(lbm_domain* d) {
 
 void launch_boundary(lbm_domain* d, void* cur) {
     BndArgs b = bnd_args(d);
-    const int nbb = (d->nb + 255) / 256 + 1;
+    const int nbb = (d->nslot_links + 255) / 256 + 1;
     if (d->storage == LBM_STORE_F64) launch_boundary_f64(ctx(d), cur, b, nbb);
     else launch_boundary_f32(ctx(d), cur, b, nbb);
     d->pending = false;
@@ -262,7 +262,9 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (!(s->tau > 0.5) || !std::isfinite(s->tau)) return LBM_EINVAL;
     if (s->rule < 0 || s->rule > 5 || s->fix < 0 || s->fix > 3) return LBM_EINVAL;
     if (s->eos < 0 || s->eos > 2 || s->collision < 0 || s->collision > 1) return LBM_EINVAL;
-    if (s->storage != LBM_STORE_F64 && s->storage != LBM_STORE_F32) return LBM_EINVAL;
+    if (s->storage != LBM_STORE_F64 && s->storage != LBM_STORE_F32 &&
+        s->storage != LBM_STORE_F32_ARITH32)
+        return LBM_EINVAL;
     if (s->reserved != 0) return LBM_EINVAL;
     if ((s->fix == LBM_FIX_B || s->fix == LBM_FIX_BAO) && s->rule != LBM_RULE_FH &&
         s->rule != LBM_RULE_MLS)
@@ -279,6 +281,13 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         return LBM_EINVAL;
     if (s->tile_h < 0) return LBM_EINVAL;
     if ((long long)nx * ny >= (1LL << 30)) return LBM_EINVAL;
+    {
+        // the nine population planes of one buffer are addressed with
+        // 32-bit byte offsets
+        const long long pitch = (nx + 63) / 64 * 64;
+        const long long esz = s->storage == LBM_STORE_F64 ? 8 : 4;
+        if (9 * (pitch * ny + 256) * esz >= (1LL << 32)) return LBM_EINVAL;
+    }
     const long long N = (long long)nx * ny;
     auto solid = [&](long long i) { return s->solid[i] != 0; };
     d->ph64 = make_phys<double>(s);
@@ -377,100 +386,123 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         flags[p] |= FL_SAVE_MOM;
         return side_idx[p];
     };
-    std::vector<int> bnode, bslot, bstart, ldir, lkind, lghost, lxf, lxff, lslotf;
+    // per-link records, grouped by node; a group never straddles a block
+    std::vector<int> lnode, lmeta, lghost, lxf, lxff, lslotb, lslotf;
     std::vector<double> lc, luw;
     const double tau = s->tau;
     long long fallbacks = 0;
-    for (long long k = 0; k < L; ++k) {
-        const LinkRec& r = recs[k];
-        const int x = r.node % nx, y = r.node / nx, a = r.dir;
-        if (k == 0 || r.node != recs[k - 1].node) {
-            bstart.push_back((int)k);
-            bnode.push_back(pidx(x, y));
-            bslot.push_back(slot_of(x, y));
-            if (d->save_f) flags[pidx(x, y)] |= FL_SAVE_F;
+    int nb = 0;
+    auto pad_to = [&](size_t n) {
+        while (lnode.size() < n) {
+            lnode.push_back(0);
+            lmeta.push_back(LK_PAD << 4);
+            lghost.push_back(0);
+            lxf.push_back(-1);
+            lxff.push_back(-1);
+            lslotb.push_back(0);
+            lslotf.push_back(-1);
+            for (int j = 0; j < 8; ++j) lc.push_back(0.0);
+            luw.push_back(0.0);
+            luw.push_back(0.0);
         }
-        const lbm_link& l = s->links[r.src];
-        const int xf = wrapi(x - cx(a), nx), yf = wrapi(y - cy(a), ny);
-        const int xff = wrapi(x - 2 * cx(a), nx), yff = wrapi(y - 2 * cy(a), ny);
-        const bool f_ok = !solid((long long)yf * nx + xf);
-        const bool ff_ok = f_ok && !solid((long long)yff * nx + xff);
-        const double q = l.q;
-        double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int kind = LK_HALFWAY, sf = -1;
-        switch (s->rule) {
-        case LBM_RULE_HALFWAY:
-            kind = LK_HALFWAY;
-            break;
-        case LBM_RULE_FH:
-        case LBM_RULE_MLS:
-            if (q < 0.5) {
-                if (s->rule == LBM_RULE_FH) {
-                    kind = LK_CHI_UB;
-                    c[3] = (2.0 * q - 1.0) / (tau - 1.0);
-                } else {
-                    c[3] = (2.0 * q - 1.0) / (tau - 2.0);
-                    if (f_ok) {
-                        kind = LK_CHI_UF;
-                        sf = slot_of(xf, yf);
-                    } else {
+    };
+    for (long long k0 = 0; k0 < L;) {
+        long long k1 = k0;
+        while (k1 < L && recs[k1].node == recs[k0].node) ++k1;
+        const int len = (int)(k1 - k0);
+        const size_t used = lnode.size() % 256;
+        if (used + len > 256) pad_to(lnode.size() + (256 - used));
+        const int x = recs[k0].node % nx, y = recs[k0].node / nx;
+        const int sb = slot_of(x, y);
+        if (d->save_f) flags[pidx(x, y)] |= FL_SAVE_F;
+        ++nb;
+        for (long long k = k0; k < k1; ++k) {
+            const LinkRec& r = recs[k];
+            const int a = r.dir;
+            const lbm_link& l = s->links[r.src];
+            const int xf = wrapi(x - cx(a), nx), yf = wrapi(y - cy(a), ny);
+            const int xff = wrapi(x - 2 * cx(a), nx), yff = wrapi(y - 2 * cy(a), ny);
+            const bool f_ok = !solid((long long)yf * nx + xf);
+            const bool ff_ok = f_ok && !solid((long long)yff * nx + xff);
+            const double q = l.q;
+            double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int kind = LK_HALFWAY, sf = -1;
+            switch (s->rule) {
+            case LBM_RULE_HALFWAY:
+                kind = LK_HALFWAY;
+                break;
+            case LBM_RULE_FH:
+            case LBM_RULE_MLS:
+                if (q < 0.5) {
+                    if (s->rule == LBM_RULE_FH) {
                         kind = LK_CHI_UB;
-                        ++fallbacks;
+                        c[3] = (2.0 * q - 1.0) / (tau - 1.0);  // Eq. (9)
+                    } else {
+                        c[3] = (2.0 * q - 1.0) / (tau - 2.0);  // Eq. (11)
+                        if (f_ok) {
+                            kind = LK_CHI_UF;
+                            sf = slot_of(xf, yf);
+                        } else {
+                            kind = LK_CHI_UB;
+                            ++fallbacks;
+                        }
                     }
+                } else {
+                    kind = LK_CHI_EXT;  // Eq. (10)
+                    c[3] = (2.0 * q - 1.0) / tau;
+                    c[4] = (q - 1.0) / q;
+                    c[5] = l.uw[0] / q;
+                    c[6] = l.uw[1] / q;
                 }
-            } else {
-                kind = LK_CHI_EXT;
-                c[3] = (2.0 * q - 1.0) / tau;
-                c[4] = (q - 1.0) / q;
-                c[5] = l.uw[0] / q;
-                c[6] = l.uw[1] / q;
+                break;
+            case LBM_RULE_IBB_LINEAR:
+            case LBM_RULE_IBB_QUADRATIC: {
+                const bool quad = s->rule == LBM_RULE_IBB_QUADRATIC;
+                if (quad && q < 0.5 && ff_ok) {  // Eq. (13)
+                    kind = LK_QUAD_F;
+                    c[0] = q * (1.0 + 2.0 * q);
+                    c[1] = 1.0 - 4.0 * q * q;
+                    c[2] = q * (1.0 - 2.0 * q);
+                } else if (quad && q >= 0.5 && f_ok) {
+                    kind = LK_QUAD_B;
+                    c[0] = 1.0 / (q * (2.0 * q + 1.0));
+                    c[1] = (2.0 * q - 1.0) / q;
+                    c[2] = (2.0 * q - 1.0) / (2.0 * q + 1.0);
+                } else if (q < 0.5 && f_ok) {  // Eq. (12)
+                    if (quad) ++fallbacks;
+                    kind = LK_LIN_F;
+                    c[0] = 2.0 * q;
+                    c[1] = 1.0 - 2.0 * q;
+                } else {
+                    if (quad || q < 0.5) ++fallbacks;
+                    kind = LK_LIN_B;
+                    c[0] = 1.0 / (2.0 * q);
+                    c[1] = (2.0 * q - 1.0) / (2.0 * q);
+                }
+                break;
             }
-            break;
-        case LBM_RULE_IBB_LINEAR:
-        case LBM_RULE_IBB_QUADRATIC: {
-            const bool quad = s->rule == LBM_RULE_IBB_QUADRATIC;
-            if (quad && q < 0.5 && ff_ok) {
-                kind = LK_QUAD_F;
-                c[0] = q * (1.0 + 2.0 * q);
-                c[1] = 1.0 - 4.0 * q * q;
-                c[2] = q * (1.0 - 2.0 * q);
-            } else if (quad && q >= 0.5 && f_ok) {
-                kind = LK_QUAD_B;
-                c[0] = 1.0 / (q * (2.0 * q + 1.0));
-                c[1] = (2.0 * q - 1.0) / q;
-                c[2] = (2.0 * q - 1.0) / (2.0 * q + 1.0);
-            } else if (q < 0.5 && f_ok) {
-                if (quad) ++fallbacks;
-                kind = LK_LIN_F;
-                c[0] = 2.0 * q;
-                c[1] = 1.0 - 2.0 * q;
-            } else {
-                if (quad || q < 0.5) ++fallbacks;
-                kind = LK_LIN_B;
-                c[0] = 1.0 / (2.0 * q);
-                c[1] = (2.0 * q - 1.0) / (2.0 * q);
+            case LBM_RULE_ZHAO_YONG:  // Eq. (14)
+                kind = LK_ZY;
+                c[0] = 2.0 * q / (1.0 + 2.0 * q);
+                c[1] = 1.0 / (1.0 + 2.0 * q);
+                break;
             }
-            break;
+            lnode.push_back(pidx(x, y));
+            lmeta.push_back(a | (kind << 4) | (len << 8) | ((int)(k - k0) << 12));
+            lghost.push_back(pidx(wrapi(x + cx(a), nx), wrapi(y + cy(a), ny)));
+            lxf.push_back(f_ok ? pidx(xf, yf) : -1);
+            lxff.push_back(ff_ok ? pidx(xff, yff) : -1);
+            lslotb.push_back(sb);
+            lslotf.push_back(sf);
+            for (int j = 0; j < 8; ++j) lc.push_back(c[j]);
+            luw.push_back(l.uw[0]);
+            luw.push_back(l.uw[1]);
         }
-        case LBM_RULE_ZHAO_YONG:
-            kind = LK_ZY;
-            c[0] = 2.0 * q / (1.0 + 2.0 * q);
-            c[1] = 1.0 / (1.0 + 2.0 * q);
-            break;
-        }
-        ldir.push_back(a);
-        lkind.push_back(kind);
-        lghost.push_back(pidx(wrapi(x + cx(a), nx), wrapi(y + cy(a), ny)));
-        lxf.push_back(f_ok ? pidx(xf, yf) : -1);
-        lxff.push_back(ff_ok ? pidx(xff, yff) : -1);
-        lslotf.push_back(sf);
-        for (int j = 0; j < 8; ++j) lc.push_back(c[j]);
-        luw.push_back(l.uw[0]);
-        luw.push_back(l.uw[1]);
+        k0 = k1;
     }
-    bstart.push_back((int)L);
-    d->nb = (int)bnode.size();
+    d->nb = nb;
     d->nl = (int)L;
+    d->nslot_links = (int)lnode.size();
     d->nslots = nslots;
     d->fallbacks = fallbacks;
 
@@ -483,7 +515,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (hipMemset(d->f[1], 0, fbytes) != hipSuccess) return LBM_EDEVICE;
     if ((rc = upload(d, &d->flags, flags))) return rc;
     if ((rc = upload(d, &d->side_idx, side_idx))) return rc;
-    if ((rc = dev_alloc(d, &d->psiw, (size_t)P * ny * d->esize))) return rc;
+    if ((rc = dev_alloc(d, &d->psiw, (size_t)P * ny * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->side_mom, (size_t)3 * std::max(nslots, 1) * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->side_f,
                         (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8)))
@@ -491,14 +523,12 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->nblocks * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
-    if ((rc = upload(d, &d->bnode, bnode))) return rc;
-    if ((rc = upload(d, &d->bslot, bslot))) return rc;
-    if ((rc = upload(d, &d->bstart, bstart))) return rc;
-    if ((rc = upload(d, &d->ldir, ldir))) return rc;
-    if ((rc = upload(d, &d->lkind, lkind))) return rc;
+    if ((rc = upload(d, &d->lnode, lnode))) return rc;
+    if ((rc = upload(d, &d->lmeta, lmeta))) return rc;
     if ((rc = upload(d, &d->lghost, lghost))) return rc;
     if ((rc = upload(d, &d->lxf, lxf))) return rc;
     if ((rc = upload(d, &d->lxff, lxff))) return rc;
+    if ((rc = upload(d, &d->lslotb, lslotb))) return rc;
     if ((rc = upload(d, &d->lslotf, lslotf))) return rc;
     if ((rc = upload(d, &d->lc, lc))) return rc;
     if ((rc = upload(d, &d->luw, luw))) return rc;

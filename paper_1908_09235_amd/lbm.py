@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm2p.so")
+LIB_PATH = os.environ.get("LBM2P_LIB", os.path.join(HERE, "liblbm2p.so"))
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESINGULAR, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 RULE = {"halfway": 0, "fh": 1, "mls": 2, "ibb_linear": 3, "ibb_quadratic": 4,
@@ -20,7 +20,7 @@ RULE = {"halfway": 0, "fh": 1, "mls": 2, "ibb_linear": 3, "ibb_quadratic": 4,
 FIX = {"none": 0, "A": 1, "B": 2, "bao": 3}
 EOS = {"none": 0, "exp": 1, "cs": 2}
 COLL = {"bgk": 0, "mrt": 1}
-STORAGE = {"f64": 0, "f32": 1}
+STORAGE = {"f64": 0, "f32": 1, "f32_arith32": 2}
 
 LINK_NP = np.dtype([("x", "<i4"), ("y", "<i4"), ("dir", "<i4"),
                     ("reserved", "<i4"), ("q", "<f8"), ("uwx", "<f8"),
