@@ -23,8 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-BYTES_PER_POP = {"f64": 8, "f32": 4, "f32_arith32": 4}
-ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32"}
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f32_arith32": 4, "f32dev": 4, "f16dev": 2}
+ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32", "f32dev": "f32", "f16dev": "f32"}
 
 
 def source_hash():
@@ -50,7 +50,8 @@ def traffic_record(storage, workload):
     return r["bytes_per_launch"]
 
 
-def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_every):
+def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_every,
+            moments=False):
     import torch
 
     from paper_1908_09235_amd import lbm
@@ -69,9 +70,44 @@ def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_every):
     lbm.lbm_set_profiling(d.h, 0)
     hist = d.mass_history(steps + 1)
     drift = float(abs(hist[-1] - hist[0]) / hist[0])
+    mom = d.moments() if moments else None
     d.close()
     return dict(seconds=t1 - t0, info=info, main_ms=main_ms / max(main_n, 1),
-                bnd_ms=bnd_ms / max(bnd_n, 1), samples=main_n, drift=drift)
+                bnd_ms=bnd_ms / max(bnd_n, 1), samples=main_n, drift=drift, mom=mom)
+
+
+def precision_leg(steps, warmup, stream, prof_every):
+    """Many cylinders with droplets, 8192 x 4096, CS at 0.86 Tc, BGK
+    tau = 0.8, MLS + B: each storage form run from the same start for the
+    same steps; errors of rho and u (max-norm relative, fluid nodes)
+    against the FP64 form."""
+    import numpy as np
+
+    from lbm_inputs import configs as cfg
+
+    p = cfg.many_cylinders()
+    fl = ~p.solid.astype(bool)
+    out = {"workload": f"{p.name}_bgk_mls_B", "steps": steps}
+    ref = None
+    for st in ("f64", "f32", "f32dev", "f16dev"):
+        r = run_gpu(p, st, steps, warmup, stream, 0, 0, prof_every, moments=True)
+        fluid = r["info"]["fluid_nodes"]
+        rec = {"arith": ARITH[st],
+               "mlups": round(fluid * steps / r["seconds"] / 1e6, 1),
+               "main_kernel_ms": round(r["main_ms"], 5),
+               "main_kernel_gbs": (round(18 * BYTES_PER_POP[st] * fluid /
+                                         (r["main_ms"] * 1e-3) / 1e9, 1)
+                                   if r["main_ms"] > 0 else None),
+               "mass_drift": r["drift"]}
+        if st == "f64":
+            ref = r["mom"]
+        else:
+            for i, nm in enumerate(("rho", "ux", "uy")):
+                den = np.max(np.abs(ref[i][fl]))
+                rec[f"err_{nm}"] = float(np.max(np.abs(r["mom"][i][fl] - ref[i][fl])) / den)
+        out[st] = rec
+    out["fluid_nodes"] = fluid
+    return out
 
 
 def cpu_baseline(p, seconds):
@@ -93,7 +129,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f32_arith32"])
+    ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_POP))
     ap.add_argument("--other-steps", type=int, default=5000,
                     help="steps of the other storage forms reported beside (0: skip)")
     ap.add_argument("--scale", type=float, default=16.0,
@@ -103,6 +139,8 @@ def main():
     ap.add_argument("--prof-every", type=int, default=1,
                     help="time the kernels of every n-th step with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision-steps", type=int, default=2000,
+                    help="steps of the 8192 x 4096 precision-form comparison (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter "
                          "calibration under rocprofv3)")
@@ -155,6 +193,10 @@ def main():
                                 if ro["main_ms"] > 0 else None),
             "mass_drift": ro["drift"], "steps": a.other_steps}
 
+    prec = None
+    if a.precision_steps > 0:
+        prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_every)
+
     cpu = None
     if a.cpu_seconds > 0:
         n, t = cpu_baseline(p, a.cpu_seconds)
@@ -185,6 +227,7 @@ def main():
                      "boundary_kernel_ms": round(r["bnd_ms"], 5)},
         "cpu_baseline": cpu,
         "also": also,
+        "precision": prec,
     }
     print(json.dumps(out), flush=True)
 

@@ -79,12 +79,18 @@ enum lbm_eos {
 
 enum lbm_collision { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 
+/* Precision forms.  The paper fixes none (its runs are double precision);
+ * every form computes the same step.  The boundary rules, boundary sums and
+ * total mass stay FP64 in every form.  The deviation forms store
+ * g_a = f_a - w_a rho_ref (w_a the lattice weights of Eq. 4) so that the
+ * stored number carries only the departure from a uniform fluid at rest. */
 enum lbm_storage {
     LBM_STORE_F64 = 0,         /* FP64 populations, FP64 arithmetic        */
     LBM_STORE_F32 = 1,         /* FP32 populations, FP64 arithmetic        */
-    LBM_STORE_F32_ARITH32 = 2  /* FP32 populations, FP32 arithmetic (the
-                                  boundary rules, boundary sums and total
-                                  mass stay FP64 in every mode)           */
+    LBM_STORE_F32_ARITH32 = 2, /* FP32 populations, FP32 arithmetic        */
+    LBM_STORE_F32DEV = 3,      /* FP32 deviations, FP32 arithmetic         */
+    LBM_STORE_F16DEV = 4       /* FP16 (IEEE binary16) deviations, FP32
+                                  arithmetic                              */
 };
 
 /* One cut link (40 bytes). */
@@ -98,9 +104,10 @@ typedef struct {
 } lbm_link;
 
 typedef struct {
-    int32_t nx, ny;            /* lattice size, each >= 3; one buffer of
-                                  nine planes must stay below 4 GiB (about
-                                  59 M nodes in FP64, 119 M in FP32)      */
+    int32_t nx, ny;            /* lattice size, each >= 3, nx*ny < 2^30;
+                                  one buffer of nine planes must stay below
+                                  4 GiB (about 59 M nodes in FP64, 119 M in
+                                  FP32)                                   */
     const uint8_t *solid;      /* host, nx*ny, nonzero = solid node         */
     const lbm_link *links;     /* host, nlinks cut links                    */
     int64_t nlinks;
@@ -130,6 +137,9 @@ typedef struct {
     int32_t tile_w;            /* launch shape of the main kernel: columns
                                   per workgroup (64, 128 or 256; 0 = auto)  */
     int32_t tile_h;            /* rows per workgroup (0 = auto)             */
+    double rho_ref;            /* reference density of the deviation forms
+                                  (>= 0; 0 = mean of rho0 over fluid nodes);
+                                  ignored by the other forms              */
 } lbm_desc;
 
 typedef struct lbm_domain lbm_domain;

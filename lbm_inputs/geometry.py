@@ -30,6 +30,11 @@ class Circle:
     def contains(self, X, Y):
         return (X - self.cx) ** 2 + (Y - self.cy) ** 2 <= self.R ** 2
 
+    def bbox(self):
+        """Row and column ranges that hold every solid node of the disc."""
+        return (int(math.floor(self.cy - self.R)) - 1, int(math.ceil(self.cy + self.R)) + 2,
+                int(math.floor(self.cx - self.R)) - 1, int(math.ceil(self.cx + self.R)) + 2)
+
     def fraction(self, xb, yb, ex, ey):
         dx, dy = xb - self.cx, yb - self.cy
         a = ex * ex + ey * ey
@@ -108,6 +113,14 @@ def build(nx: int, ny: int, shapes: Sequence):
     owner = np.full((ny, nx), -1, dtype=np.int32)
     for k, sh in enumerate(shapes):
         assert sh.fits(nx, ny), f"shape {k} does not fit the {nx}x{ny} domain"
+        if hasattr(sh, "bbox"):   # a shape that fits lies inside its box
+            y0, y1, x0, x1 = sh.bbox()
+            y0, y1, x0, x1 = max(y0, 0), min(y1, ny), max(x0, 0), min(x1, nx)
+            m = sh.contains(X[y0:y1, x0:x1], Y[y0:y1, x0:x1])
+            sub = owner[y0:y1, x0:x1]
+            assert not np.any(sub[m] >= 0), "overlapping shapes"
+            sub[m] = k
+            continue
         m = sh.contains(X, Y)
         assert not np.any(owner[m] >= 0), "overlapping shapes"
         owner[m] = k

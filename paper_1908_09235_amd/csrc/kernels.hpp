@@ -80,11 +80,18 @@ __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned v, unsigned s
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
 }
 template <>
+__device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+}
+template <>
 __device__ __forceinline__ uint8_t bload<uint8_t>(rsrc_t r, unsigned v, unsigned s) {
     return __builtin_amdgcn_raw_buffer_load_b8(r, v, s, 0);
 }
 __device__ __forceinline__ void bstore(float x, rsrc_t r, unsigned v, unsigned s) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+}
+__device__ __forceinline__ void bstore(_Float16 x, rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 0);
 }
 __device__ __forceinline__ void bstore(double x, rsrc_t r, unsigned v, unsigned s) {
     typedef __attribute__((ext_vector_type(2))) unsigned u2;
@@ -107,8 +114,9 @@ struct RowLoad {
     uint8_t fl, hfl;
 };
 
-// MOMENTS: write rho, u at every node instead of colliding and storing
-template <typename S, typename R, int EOS, bool MOMENTS>
+// MOMENTS: write rho, u at every node instead of colliding and storing.
+// DEV: populations are stored as deviations g = f - w rho_ref.
+template <typename S, typename R, int EOS, bool MOMENTS, bool DEV>
 __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
     __shared__ R ring[4][kMaxTileW + 2];
     __shared__ double wsum[kMaxTileW / 64];
@@ -190,7 +198,8 @@ __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
         R f[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) f[q] = R(fs[q]);
-        return (fl & FL_SOLID) ? pw : psi_of<EOS, R>(dens<R>(f), ph);
+        const R rho = DEV ? ph.rref + dens<R>(f) : dens<R>(f);
+        return (fl & FL_SOLID) ? pw : psi_of<EOS, R>(rho, ph);
     };
     auto publish = [&](const RowLoad<S, R>& L, int slot) {
         if (act) ring[slot][tid + 1] = psi_node(L.f, L.pw, L.fl);
@@ -209,11 +218,12 @@ __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
         publish(Ln, sp);
         __syncthreads();
         if (act && !(Lc.fl & FL_SOLID)) {
-            R fc[9];
+            R fc[9];  // stored form: f, or deviations g
 #pragma unroll
             for (int q = 0; q < 9; ++q) fc[q] = R(Lc.f[q]);
             const int c = tid + 1;
-            const R rho = dens<R>(fc);
+            const R drho = dens<R>(fc);
+            const R rho = DEV ? ph.rref + drho : drho;
             const R irho = rcp(rho);
             R Fx = R(0), Fy = R(0);
             if constexpr (EOS != EOS_NONE) {
@@ -240,27 +250,32 @@ __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
             if constexpr (MOMENTS) {
                 const long long o = (long long)y * a.nx + x;
                 const long long n2 = (long long)a.nx * a.ny;
-                a.mom_out[o] = double(rho);
+                a.mom_out[o] = DEV ? double(ph.rref) + double(drho) : double(rho);
                 a.mom_out[n2 + o] = double(ux);
                 a.mom_out[2 * n2 + o] = double(uy);
             } else {
-                msum += double(rho);
+                // FP64 density (the deviation forms add the reference here)
+                const double rho_d = DEV ? double(ph.rref) + double(drho) : double(rho);
+                msum += rho_d;
                 if (Lc.fl & (FL_SAVE_MOM | FL_SAVE_F)) {
                     const int slot = a.side_idx[(unsigned)y * pitch + x];
                     if (Lc.fl & FL_SAVE_MOM) {
-                        a.side_mom[3 * slot + 0] = double(rho);
+                        a.side_mom[3 * slot + 0] = rho_d;
                         a.side_mom[3 * slot + 1] = double(ux);
                         a.side_mom[3 * slot + 2] = double(uy);
                     }
                     if (Lc.fl & FL_SAVE_F) {
 #pragma unroll
-                        for (int q = 0; q < 9; ++q) a.side_f[9 * slot + q] = double(fc[q]);
+                        for (int q = 0; q < 9; ++q)
+                            a.side_f[9 * slot + q] =
+                                DEV ? double(fc[q]) + wt(q) * double(ph.rref) : double(fc[q]);
                     }
                 }
-                collide<R>(fc, rho, ux, uy, Fx, Fy, ph);
+                R dh[9];
+                collide<R>(fc, rho, drho, ux, uy, Fx, Fy, ph, dh);
                 const unsigned r0 = (unsigned)y * pitch * ES;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) bstore(S(fc[q]), rd, x * ES, q * pb + r0);
+                for (int q = 0; q < 9; ++q) bstore(S(fc[q] + dh[q]), rd, x * ES, q * pb + r0);
             }
         } else if (MOMENTS && act) {
             const long long o = (long long)y * a.nx + x;
@@ -360,6 +375,7 @@ struct BndArgs {
     const double* __restrict__ side_mom;
     const double* __restrict__ side_f;
     long long plane;
+    double rref;                     // deviation storage reference (else 0)
     int fix;                         // 0 none, 1 A, 2 B, 3 Bao
     // reduction of the previous main launch's mass partials (last block)
     const double* __restrict__ partial;
@@ -372,7 +388,7 @@ struct BndArgs {
 
 constexpr int LK_PAD = 15;
 
-template <typename S>
+template <typename S, bool DEV>
 __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
     if (blockIdx.x == gridDim.x - 1) {
         if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
@@ -387,6 +403,10 @@ __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) 
     const int len = (meta >> 8) & 15, pos = (meta >> 12) & 15;
     const bool active = kind != LK_PAD;
     const long long P = b.plane;
+    // stored form -> population
+    auto ld = [&](int q, int n) {
+        return DEV ? double(A[q * P + n]) + wt(q) * b.rref : double(A[q * P + n]);
+    };
     int node = 0;
     double fab = 0.0, r = 0.0, ch = 0.0, bk = 0.0, wl = 0.0;
     if (active) {
@@ -396,7 +416,7 @@ __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) 
         const double* mom = b.side_mom + 3 * b.lslotb[i];
         const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
         const double ex = double(cx(d)), ey = double(cy(d));
-        fab = double(A[d * P + node]);
+        fab = ld(d, node);
         const double uwx = b.luw[2 * i], uwy = b.luw[2 * i + 1];
         // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
         wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
@@ -423,17 +443,15 @@ __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) 
             bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
             r = (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
         } else if (kind == LK_LIN_F) {
-            r = c[0] * fab + c[1] * double(A[d * P + b.lxf[i]]);
+            r = c[0] * fab + c[1] * ld(d, b.lxf[i]);
         } else if (kind == LK_LIN_B) {
-            r = c[0] * fab + c[1] * double(A[od * P + node]);
+            r = c[0] * fab + c[1] * ld(od, node);
         } else if (kind == LK_QUAD_F) {
-            r = c[0] * fab + c[1] * double(A[d * P + b.lxf[i]]) -
-                c[2] * double(A[d * P + b.lxff[i]]);
+            r = c[0] * fab + c[1] * ld(d, b.lxf[i]) - c[2] * ld(d, b.lxff[i]);
         } else if (kind == LK_QUAD_B) {
-            r = c[0] * fab + c[1] * double(A[od * P + node]) -
-                c[2] * double(A[od * P + b.lxf[i]]);
+            r = c[0] * fab + c[1] * ld(od, node) - c[2] * ld(od, b.lxf[i]);
         } else {  // LK_ZY, Eq. (14)
-            r = c[0] * double(A[od * P + node]) + c[1] * b.side_f[9 * b.lslotb[i] + d];
+            r = c[0] * ld(od, node) + c[1] * b.side_f[9 * b.lslotb[i] + d];
         }
     }
     s_fab[tid] = fab;
@@ -471,7 +489,7 @@ __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) 
         }
         __syncthreads();
     }
-    if (active) A[opp(d) * P + b.lghost[i]] = S(r);
+    if (active) A[opp(d) * P + b.lghost[i]] = S(DEV ? r - wt(d) * b.rref : r);
     if (head && b.fix == 1) {
         // Eq. (15) without the wall momentum, added to the rest population
         // (Eq. 18)
@@ -491,7 +509,7 @@ __global__ void k_init_scatter(S* __restrict__ B, const uint8_t* __restrict__ fl
                                const double* __restrict__ rho0,
                                const double* __restrict__ ux0,
                                const double* __restrict__ uy0, int nx, int ny,
-                               int pitch, long long plane) {
+                               int pitch, long long plane, double rref) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= nx || y >= ny) return;
@@ -506,7 +524,7 @@ __global__ void k_init_scatter(S* __restrict__ B, const uint8_t* __restrict__ fl
         int xs = x - cx(a), ys = y - cy(a);
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
         ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-        B[a * plane + ys * pitch + xs] = S(f);
+        B[a * plane + ys * pitch + xs] = S(f - wt(a) * rref);
     }
 }
 

@@ -49,6 +49,7 @@ struct Phys {
     R G, gx, gy;
     R e0, e1, e2, e3;  // EOS parameters
     R p2G;             // 2 / G
+    R rref;            // reference density of deviation storage (else 0)
     R s[9];        // relaxation rates of the nine moments (BGK: all 1/tau)
 };
 
@@ -106,9 +107,14 @@ __host__ __device__ __forceinline__ R psi_of(R rho, const Phys<R>& p) {
 // directions paired, and the rest increment closes the mass balance, so
 // the arithmetic acts on the small non-equilibrium parts and each
 // expression is exactly symmetric under lattice reflections.
+//
+// h holds the populations in their stored form: f itself, or the deviations
+// g = f - w rho_ref; drho = sum h (= rho - rho_ref).  The lattice weights
+// have e- and eps-moments -2 and 1 and no others, so only those two moments
+// see the reference.  The increments are returned in dh.
 template <typename R>
-__device__ __forceinline__ void collide(R f[9], R rho, R ux, R uy, R Fx, R Fy,
-                                        const Phys<R>& p) {
+__device__ __forceinline__ void collide(const R f[9], R rho, R drho, R ux, R uy, R Fx,
+                                        R Fy, const Phys<R>& p, R dh[9]) {
     const R s1 = f[1] + f[3], s2 = f[2] + f[4], c1 = f[5] + f[7], c2 = f[6] + f[8];
     const R d1 = f[1] - f[3], d2 = f[2] - f[4], e1 = f[5] - f[7], e2 = f[6] - f[8];
     const R sa = s1 + s2, sd = c1 + c2;
@@ -120,8 +126,8 @@ __device__ __forceinline__ void collide(R f[9], R rho, R ux, R uy, R Fx, R Fy,
     const R uxx = ux * ux, uyy = uy * uy, usq = uxx + uyy;
     const R uF = ux * Fx + uy * Fy;
     const R ru2 = R(3) * rho * usq;
-    const R De = p.s[1] * ((ru2 - (rho + rho)) - m_e) + (R(1) - R(0.5) * p.s[1]) * (R(6) * uF);
-    const R Dp = p.s[2] * ((rho - ru2) - m_p) - (R(1) - R(0.5) * p.s[2]) * (R(6) * uF);
+    const R De = p.s[1] * ((ru2 - (drho + drho)) - m_e) + (R(1) - R(0.5) * p.s[1]) * (R(6) * uF);
+    const R Dp = p.s[2] * ((drho - ru2) - m_p) - (R(1) - R(0.5) * p.s[2]) * (R(6) * uF);
     const R Dqx = -p.s[4] * (rho * ux + m_qx) - (R(1) - R(0.5) * p.s[4]) * Fx;
     const R Dqy = -p.s[6] * (rho * uy + m_qy) - (R(1) - R(0.5) * p.s[6]) * Fy;
     const R Dxx = p.s[7] * (rho * (uxx - uyy) - m_xx) +
@@ -142,15 +148,15 @@ __device__ __forceinline__ void collide(R f[9], R rho, R ux, R uy, R Fx, R Fy,
     const R g5 = bp + (P + Q), g7 = bp - (P + Q);
     const R g6 = bm + (Q - P), g8 = bm - (Q - P);
     const R g0 = -(((g1 + g3) + (g2 + g4)) + ((g5 + g7) + (g6 + g8)));
-    f[0] += g0;
-    f[1] += g1;
-    f[2] += g2;
-    f[3] += g3;
-    f[4] += g4;
-    f[5] += g5;
-    f[6] += g6;
-    f[7] += g7;
-    f[8] += g8;
+    dh[0] = g0;
+    dh[1] = g1;
+    dh[2] = g2;
+    dh[3] = g3;
+    dh[4] = g4;
+    dh[5] = g5;
+    dh[6] = g6;
+    dh[7] = g7;
+    dh[8] = g8;
 }
 
 }  // namespace lbm

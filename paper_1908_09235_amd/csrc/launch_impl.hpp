@@ -16,11 +16,12 @@ Phys<R> convert(const Phys<double>& d) {
     p.e2 = R(d.e2);
     p.e3 = R(d.e3);
     p.p2G = R(d.p2G);
+    p.rref = R(d.rref);
     for (int i = 0; i < 9; ++i) p.s[i] = R(d.s[i]);
     return p;
 }
 
-template <typename S, typename R, int EOS, bool MOM>
+template <typename S, typename R, int EOS, bool MOM, bool DEV>
 void main_t(const Ctx& c, const S* src, S* dst) {
     MainArgs<S> a{};
     a.src = src;
@@ -39,28 +40,28 @@ void main_t(const Ctx& c, const S* src, S* dst) {
     a.tile_h = c.tile_h;
     a.nsegs = c.nsegs;
     a.nstrips = c.nstrips;
-    hipLaunchKernelGGL((k_main<S, R, EOS, MOM>), dim3(c.nblocks), dim3(c.tile_w), 0,
+    hipLaunchKernelGGL((k_main<S, R, EOS, MOM, DEV>), dim3(c.nblocks), dim3(c.tile_w), 0,
                        c.stream, a, convert<R>(c.ph));
 }
 
-template <typename S, typename R, bool MOM>
+template <typename S, typename R, bool MOM, bool DEV>
 void main_s(const Ctx& c, const void* src, void* dst) {
     const S* s = static_cast<const S*>(src);
     S* t = static_cast<S*>(dst);
-    if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, MOM>(c, s, t);
-    else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, MOM>(c, s, t);
-    else main_t<S, R, EOS_CS, MOM>(c, s, t);
+    if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, MOM, DEV>(c, s, t);
+    else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, MOM, DEV>(c, s, t);
+    else main_t<S, R, EOS_CS, MOM, DEV>(c, s, t);
 }
 
-template <typename S, typename R>
+template <typename S, typename R, bool DEV = false>
 void main_any(const Ctx& c, const void* src, void* dst, bool moments) {
-    if (moments) main_s<S, R, true>(c, src, dst);
-    else main_s<S, R, false>(c, src, dst);
+    if (moments) main_s<S, R, true, DEV>(c, src, dst);
+    else main_s<S, R, false, DEV>(c, src, dst);
 }
 
-template <typename S>
+template <typename S, bool DEV = false>
 void boundary_any(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
-    hipLaunchKernelGGL(k_boundary<S>, dim3(nblocks), dim3(256), 0, c.stream,
+    hipLaunchKernelGGL((k_boundary<S, DEV>), dim3(nblocks), dim3(256), 0, c.stream,
                        static_cast<S*>(cur), b);
 }
 
@@ -80,7 +81,7 @@ void init_any(const Ctx& c, const double* rw, const double* r0, const double* u0
         hipLaunchKernelGGL((k_psi_wall<R, EOS_NONE>), g, dim3(256), 0, c.stream, psiw, rw,
                            c.flags, c.nx, c.ny, c.pitch, ph);
     hipLaunchKernelGGL(k_init_scatter<S>, g, dim3(256), 0, c.stream, static_cast<S*>(buf),
-                       c.flags, r0, u0, v0, c.nx, c.ny, c.pitch, c.plane);
+                       c.flags, r0, u0, v0, c.nx, c.ny, c.pitch, c.plane, c.ph.rref);
 }
 
 }  // namespace lbm

@@ -93,6 +93,10 @@ void free_domain(lbm_domain* d) {
 
 inline int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
+inline long long storage_bytes(int storage) {
+    return storage == LBM_STORE_F64 ? 8 : storage == LBM_STORE_F16DEV ? 2 : 4;
+}
+
 template <typename R>
 Phys<R> make_phys(const lbm_desc* s) {
     Phys<R> p{};
@@ -162,6 +166,7 @@ BndArgs bnd_args(lbm_domain* d) {
     b.side_mom = d->side_mom;
     b.side_f = d->side_f;
     b.plane = d->plane;
+    b.rref = d->ph64.rref;
     b.fix = d->fix;
     b.partial = d->partial;
     b.np = d->nblocks;
@@ -262,9 +267,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (!(s->tau > 0.5) || !std::isfinite(s->tau)) return LBM_EINVAL;
     if (s->rule < 0 || s->rule > 5 || s->fix < 0 || s->fix > 3) return LBM_EINVAL;
     if (s->eos < 0 || s->eos > 2 || s->collision < 0 || s->collision > 1) return LBM_EINVAL;
-    if (s->storage != LBM_STORE_F64 && s->storage != LBM_STORE_F32 &&
-        s->storage != LBM_STORE_F32_ARITH32)
-        return LBM_EINVAL;
+    if (s->storage < LBM_STORE_F64 || s->storage > LBM_STORE_F16DEV) return LBM_EINVAL;
+    if (!(s->rho_ref >= 0.0) || !std::isfinite(s->rho_ref)) return LBM_EINVAL;
     if (s->reserved != 0) return LBM_EINVAL;
     if ((s->fix == LBM_FIX_B || s->fix == LBM_FIX_BAO) && s->rule != LBM_RULE_FH &&
         s->rule != LBM_RULE_MLS)
@@ -285,7 +289,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         // the nine population planes of one buffer are addressed with
         // 32-bit byte offsets
         const long long pitch = (nx + 63) / 64 * 64;
-        const long long esz = s->storage == LBM_STORE_F64 ? 8 : 4;
+        const long long esz = storage_bytes(s->storage);
         if (9 * (pitch * ny + 256) * esz >= (1LL << 32)) return LBM_EINVAL;
     }
     const long long N = (long long)nx * ny;
@@ -351,6 +355,19 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
             return LBM_EINVAL;
     }
     d->fluid = fluid;
+    if (s->storage == LBM_STORE_F32DEV || s->storage == LBM_STORE_F16DEV) {
+        double rref = s->rho_ref;
+        if (rref == 0.0 && fluid > 0) {
+            double sum = 0.0;
+            for (long long i = 0; i < N; ++i)
+                if (!solid(i)) sum += s->rho0[i];
+            rref = sum / (double)fluid;
+        }
+        // rounded to FP32 so that the FP32 main kernel and the FP64
+        // boundary kernel decode with the same reference
+        d->ph64.rref = double(float(rref));
+        d->ph32.rref = float(rref);
+    }
 
     // ---- layout
     d->nx = nx;
@@ -358,7 +375,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->pitch = (nx + 63) / 64 * 64;
     d->plane = (long long)d->pitch * ny + 256;  // stagger the nine planes
     d->storage = s->storage;
-    d->esize = s->storage == LBM_STORE_F64 ? 8 : 4;
+    d->esize = (size_t)storage_bytes(s->storage);
     d->eos = s->eos;
     d->coll = s->collision;
     d->rule = s->rule;

@@ -20,7 +20,7 @@ RULE = {"halfway": 0, "fh": 1, "mls": 2, "ibb_linear": 3, "ibb_quadratic": 4,
 FIX = {"none": 0, "A": 1, "B": 2, "bao": 3}
 EOS = {"none": 0, "exp": 1, "cs": 2}
 COLL = {"bgk": 0, "mrt": 1}
-STORAGE = {"f64": 0, "f32": 1, "f32_arith32": 2}
+STORAGE = {"f64": 0, "f32": 1, "f32_arith32": 2, "f32dev": 3, "f16dev": 4}
 
 LINK_NP = np.dtype([("x", "<i4"), ("y", "<i4"), ("dir", "<i4"),
                     ("reserved", "<i4"), ("q", "<f8"), ("uwx", "<f8"),
@@ -49,7 +49,8 @@ class lbm_desc(C.Structure):
                 ("ux0", C.POINTER(C.c_double)),
                 ("uy0", C.POINTER(C.c_double)),
                 ("history_capacity", C.c_int64), ("stream", C.c_void_p),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32),
+                ("rho_ref", C.c_double)]
 
 
 assert C.sizeof(lbm_link) == 40 and LINK_NP.itemsize == 40
@@ -114,7 +115,7 @@ def _dptr(a):
 
 
 def make_desc(problem, storage="f64", tile_w=0, tile_h=0, stream=None,
-              history_capacity=0):
+              history_capacity=0, rho_ref=0.0):
     """Marshal a problem description into an lbm_desc.
 
     Returns (desc, keepalive); the arrays in keepalive must outlive the
@@ -154,12 +155,14 @@ def make_desc(problem, storage="f64", tile_w=0, tile_h=0, stream=None,
     d.history_capacity = history_capacity
     d.stream = stream
     d.tile_w, d.tile_h = tile_w, tile_h
+    d.rho_ref = rho_ref
     return d, keep
 
 
 def lbm_create_domain(problem, storage="f64", tile_w=0, tile_h=0, stream=None,
-                      history_capacity=0):
-    d, keep = make_desc(problem, storage, tile_w, tile_h, stream, history_capacity)
+                      history_capacity=0, rho_ref=0.0):
+    d, keep = make_desc(problem, storage, tile_w, tile_h, stream, history_capacity,
+                        rho_ref)
     h = _H()
     _check(lib().lbm_create_domain(C.byref(d), C.byref(h)), "lbm_create_domain")
     del keep

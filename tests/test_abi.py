@@ -109,9 +109,47 @@ def test_bad_launch_shape_and_storage_are_rejected(L):
             L.lbm_create_domain(p, **kw)
         assert e.value.code == L.LBM_EINVAL
     d, keep = L.make_desc(p)
-    d.storage = 7
     h = ctypes.c_void_p()
-    assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+    for st in (-1, 5, 7):
+        d.storage = st
+        assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+    d.storage = L.STORAGE["f16dev"]
+    for rr in (-1.0, float("nan"), float("inf")):
+        d.rho_ref = rr
+        assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+    d.rho_ref = 0.0
     d.storage = 0
     d.reserved = 1
     assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+
+
+def test_binding_struct_layout_matches_header(L, tmp_path):
+    """The ctypes mirrors of lbm_desc and lbm_link have the header's field
+    offsets and sizes (a C program built from the header prints them)."""
+    import shutil
+    import subprocess
+    from pathlib import Path
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = Path(__file__).resolve().parents[1] / "include"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm2p.h"',
+             'int main(void) {']
+    for st, cls in (("lbm_desc", L.lbm_desc), ("lbm_link", L.lbm_link)):
+        lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
+        for name, _ in cls._fields_:
+            lines.append(f'printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", str(inc), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        st, name, val = line.split()
+        got[(st, name)] = int(val)
+    for st, cls in (("lbm_desc", L.lbm_desc), ("lbm_link", L.lbm_link)):
+        assert got[(st, "sizeof")] == ctypes.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)
