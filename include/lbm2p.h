@@ -206,6 +206,104 @@ int lbm_info(lbm_domain *d, int64_t out[8]);
 void lbm_destroy(lbm_domain *d);
 const char *lbm_status_string(int status);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent domains (instances) advanced together.
+ * Each instance is a complete domain as above (its own geometry, EOS
+ * parameters, tau or MRT rates, rule, fix and state) and computes exactly
+ * what lbm_step computes for it alone.  All instances of a batch share the
+ * storage form and the EOS kind.  Device memory for all of them comes from
+ * one arena allocated at creation; instances are built on a stream of the
+ * batch's own while earlier work runs on the compute stream.  A step of the
+ * batch is three launches over all instances (boundary pass, main pass,
+ * per-instance mass reduction), replayed from a captured HIP graph.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+typedef struct {
+    int32_t storage;        /* enum lbm_storage of every instance          */
+    int32_t eos;            /* enum lbm_eos of every instance              */
+    int32_t max_instances;  /* instance slots, 1 .. 2^20                    */
+    int32_t tile_w;         /* main-pass tile columns: 64, 128, 256 (0=256) */
+    int32_t tile_h;         /* main-pass tile rows: >= 8 (0 = 16)           */
+    int32_t persistent;     /* 1: a resident grid takes tiles from per-XCD
+                               queues; 0: one workgroup per tile           */
+    int32_t graph_steps;    /* steps per captured graph (0 = 32; < 0: no
+                               graph, plain launches)                      */
+    int32_t reserved;       /* must be 0                                    */
+    int64_t arena_bytes;    /* device memory for all instances (> 0)        */
+    void *stream;           /* compute stream (NULL: the batch makes one)   */
+} lbm_batch_desc;
+
+/* Errors: LBM_EINVAL (a field out of range), LBM_ENOMEM (the arena or the
+ * tables), LBM_EDEVICE. */
+int lbm_batch_create(const lbm_batch_desc *bd, lbm_batch **out);
+
+/* Build an instance from a descriptor (as lbm_create_domain: same
+ * validation and errors; desc->stream, tile_w and tile_h are ignored) that
+ * will run `steps` steps and then stop.  *slot receives its slot index.
+ * LBM_ENOMEM when no slot is free or the arena has no room for it; the
+ * batch is unchanged then.  The instance joins the next lbm_batch_run. */
+int lbm_batch_add(lbm_batch *b, const lbm_desc *desc, int64_t steps, int32_t *slot);
+
+/* Enqueue n steps for every instance (each stops after its own count) on
+ * the compute stream; waits for the previous run first. */
+int lbm_batch_run(lbm_batch *b, int64_t n);
+int lbm_batch_sync(lbm_batch *b);
+
+/* Per instance, after waiting for the batch: the current step, the steps
+ * still to run, and the first step with a non-finite total mass (or -1;
+ * an unstable instance stops). */
+int lbm_batch_status(lbm_batch *b, int32_t slot, int64_t *t, int64_t *remaining,
+                     int64_t *unstable_step);
+/* As lbm_moments and lbm_mass_history, for one instance. */
+int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, double *uy);
+int lbm_batch_mass_history(lbm_batch *b, int32_t slot, double *out, int64_t cap,
+                           int64_t *n_written);
+/* Free an instance's memory and its slot. */
+int lbm_batch_remove(lbm_batch *b, int32_t slot);
+
+/* Autotuner: runs steps_per_trial real steps of the batch (after one
+ * warm-up step) under each main-pass shape (tile_w 64/128/256, tile_h
+ * 8/16/32, persistent or not), keeps the fastest and reports it in out:
+ * tile_w, tile_h, persistent, microseconds per step.  The steps count as
+ * steps of the instances; results do not depend on the shape. */
+int lbm_batch_tune(lbm_batch *b, int64_t steps_per_trial, int32_t out[4]);
+
+/* [0] instances, [1] main-pass tiles, [2] link blocks, [3] arena bytes,
+ * [4] arena bytes in use, [5] tile_w, [6] tile_h, [7] persistent. */
+int lbm_batch_info(lbm_batch *b, int64_t out[8]);
+void lbm_batch_destroy(lbm_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Served form: a request queue in front of a batch (continuous batching).
+ * lbm_server_submit queues a request (a descriptor and a step count); the
+ * arrays the descriptor points to must stay valid until the request is
+ * admitted.  Each lbm_server_progress call is one scheduling round: it
+ * waits for the chunk of steps in flight, reports the requests that
+ * finished, launches the next chunk_steps steps for every resident request,
+ * and while that chunk runs admits queued requests in arrival order as long
+ * as their instance fits in the arena and a slot is free.  A finished
+ * request keeps its memory until lbm_server_release.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_server lbm_server;
+
+int lbm_server_create(const lbm_batch_desc *bd, int64_t chunk_steps, lbm_server **out);
+int lbm_server_submit(lbm_server *s, const lbm_desc *desc, int64_t steps, int64_t *id);
+/* done_ids receives the ids that finished in this round (at most cap;
+ * LBM_EINVAL if more finished, all still reported by *n_done = cap). */
+int lbm_server_progress(lbm_server *s, int64_t *done_ids, int64_t cap, int64_t *n_done);
+/* A finished request: its final rho, u (host arrays of nx*ny, any may be
+ * NULL), mass[0] = M(0) (NaN if it left the history ring) and mass[1] =
+ * the final M, the steps it ran and its first unstable step (or -1). */
+int lbm_server_result(lbm_server *s, int64_t id, double *rho, double *ux, double *uy,
+                      double mass[2], int64_t *steps_done, int64_t *unstable_step);
+int lbm_server_release(lbm_server *s, int64_t id);
+/* [0] queued, [1] running, [2] finished and not released, [3] arena bytes
+ * in use, [4] arena bytes, [5] chunks launched, [6] admitted, [7] rejected
+ * (invalid descriptors, or too large for the arena). */
+int lbm_server_info(lbm_server *s, int64_t out[8]);
+void lbm_server_destroy(lbm_server *s);
+
 #ifdef __cplusplus
 }
 #endif

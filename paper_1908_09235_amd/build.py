@@ -12,6 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 # written (exact agreement with a left-to-right evaluation of the method's
 # formulas); the FP32 kernels may fuse multiply-adds.
 UNITS = [("lbm2p.hip", ["-ffp-contract=off"]),
+         ("batch.hip", ["-ffp-contract=off"]),
          ("launch_f64.hip", ["-ffp-contract=off"]),
          ("launch_f32.hip", ["-ffp-contract=fast"])]
 DEPS = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [

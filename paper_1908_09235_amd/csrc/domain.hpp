@@ -1,0 +1,93 @@
+// Host-side state of one domain, shared by the single-domain API
+// (lbm2p.hip) and the batched and served forms (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <map>
+#include <vector>
+
+#include "../../include/lbm2p.h"
+#include "launch.hpp"
+
+namespace lbm {
+
+// Device memory carved out of one hipMalloc: first fit over 256-byte
+// granules with a coalescing free list.  Bookkeeping is host-only, so
+// taking and returning memory never synchronises the device; the caller
+// returns a block only once no queued work uses it.
+class Arena {
+  public:
+    ~Arena();
+    int init(size_t bytes);  // lbm_status
+    void* alloc(size_t bytes);  // nullptr if nothing fits
+    void release(void* p);
+    size_t capacity() const { return cap_; }
+    size_t used() const { return used_; }
+    size_t largest_free() const;
+
+  private:
+    char* base_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> bytes
+    std::map<size_t, size_t> live_;  // offset -> bytes
+};
+
+}  // namespace lbm
+
+struct lbm_domain {
+    int nx = 0, ny = 0, pitch = 0;
+    long long plane = 0;
+    int storage = 0, eos = 0, coll = 0, rule = 0, fix = 0;
+    int tile_w = 0, tile_h = 0, nstrips = 0, nsegs = 0, nblocks = 0;
+    size_t esize = 8;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t* flags = nullptr;
+    void* psiw = nullptr;
+    int* side_idx = nullptr;
+    double* side_mom = nullptr;
+    double* side_f = nullptr;
+    int nslots = 0;
+    bool save_f = false;
+    double* partial = nullptr;
+    double* hist = nullptr;
+    long long* unstable = nullptr;
+    double* mom_out = nullptr;
+    int nb = 0, nl = 0;
+    int nslot_links = 0;
+    int *lnode = nullptr, *lmeta = nullptr, *lghost = nullptr, *lxf = nullptr,
+        *lxff = nullptr, *lslotb = nullptr, *lslotf = nullptr;
+    double *lc = nullptr, *luw = nullptr;
+    long long cap = 0, t = 0;
+    bool pending = false;
+    long long pending_t = 0;
+    hipStream_t stream = nullptr;
+    lbm::Phys<double> ph64{};
+    lbm::Phys<float> ph32{};
+    size_t bytes = 0;
+    long long fluid = 0, fallbacks = 0;
+    std::vector<void*> allocs;
+    lbm::Arena* arena = nullptr;  // sub-allocate from it instead of hipMalloc
+    int partial_cap = 0;          // partials held (enough for 64 x 8 tiles)
+    int prof = 0;                 // record every prof-th step (0: off)
+    int nrec = 0;
+    std::vector<hipEvent_t> ev;
+    double main_ms = 0, bnd_ms = 0;
+    long long main_n = 0, bnd_n = 0;
+};
+
+namespace lbm {
+
+// Build a domain from a descriptor (all device work on desc->stream, which
+// is synchronised before returning).  With an arena, device memory comes
+// from it.
+int domain_create(const lbm_desc* desc, Arena* arena, lbm_domain** out);
+void domain_free(lbm_domain* d);
+// The tile shape of the main pass (tile_w 64/128/256, tile_h >= 1 with at
+// most partial_cap tiles); the next launch uses it.
+int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h);
+Ctx domain_ctx(lbm_domain* d);
+
+}  // namespace lbm

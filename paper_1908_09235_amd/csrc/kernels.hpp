@@ -114,10 +114,13 @@ struct RowLoad {
     uint8_t fl, hfl;
 };
 
+// One tile of the main pass: strip `strip` of tile_w = blockDim.x columns,
+// rows of segment `seg`.  Writes the tile's mass partial to partial[tile].
 // MOMENTS: write rho, u at every node instead of colliding and storing.
 // DEV: populations are stored as deviations g = f - w rho_ref.
 template <typename S, typename R, int EOS, bool MOMENTS, bool DEV>
-__global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
+__device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& ph,
+                                          int tile) {
     __shared__ R ring[4][kMaxTileW + 2];
     __shared__ double wsum[kMaxTileW / 64];
     constexpr unsigned ES = sizeof(S), RS = sizeof(R);
@@ -132,7 +135,6 @@ __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
 
     const int tid = threadIdx.x;
     const int W = blockDim.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int seg = tile / a.nstrips, strip = tile - seg * a.nstrips;
     const int x0 = strip * W;
     const int ncols = min(W, a.nx - x0);
@@ -310,9 +312,14 @@ __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
         if (tid == 0) {
             double t = 0.0;
             for (int w = 0; w < (W + 63) / 64; ++w) t += wsum[w];
-            a.partial[blockIdx.x] = t;
+            a.partial[tile] = t;
         }
     }
+}
+
+template <typename S, typename R, int EOS, bool MOMENTS, bool DEV>
+__global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
+    main_tile<S, R, EOS, MOMENTS, DEV>(a, ph, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Sum the main kernel's partials in a fixed order into the history ring.
@@ -388,16 +395,14 @@ struct BndArgs {
 
 constexpr int LK_PAD = 15;
 
+// Block `blk` of 256 link slots.
 template <typename S, bool DEV>
-__global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
-    if (blockIdx.x == gridDim.x - 1) {
-        if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
-        return;
-    }
+__device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs& b,
+                                               int blk) {
     __shared__ double s_fab[256], s_inc[256], s_chi[256], s_br[256], s_wall[256];
     __shared__ double s_rhos[256];
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * 256 + tid;
+    const int i = blk * 256 + tid;
     const int meta = i < b.nslot ? b.lmeta[i] : (LK_PAD << 4);
     const int d = meta & 15, kind = (meta >> 4) & 15;
     const int len = (meta >> 8) & 15, pos = (meta >> 12) & 15;
@@ -502,6 +507,16 @@ __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) 
     }
 }
 
+// The last block reduces the previous main pass's mass partials.
+template <typename S, bool DEV>
+__global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
+    if (blockIdx.x == gridDim.x - 1) {
+        if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
+        return;
+    }
+    boundary_block<S, DEV>(A, b, blockIdx.x);
+}
+
 // f(0) = f_eq(rho0, u0), stored where the first pull reads it:
 // buffer[a][x - e_a] = f_a(0)(x)
 template <typename S>
@@ -538,6 +553,183 @@ __global__ void k_psi_wall(R* __restrict__ psiw, const double* __restrict__ rho_
     if (x >= nx || y >= ny) return;
     const int i = y * pitch + x;
     psiw[i] = (flags[i] & FL_SOLID) ? psi_of<EOS, R>(R(rho_wall[y * nx + x]), ph) : R(0);
+}
+
+// ---------------------------------------------------------------- batches
+// Many independent instances advance together: per step one boundary
+// launch over the link blocks of all instances, one main launch over the
+// tiles of all instances and one launch that reduces each instance's mass
+// partials.  Everything a launch needs about an instance lives in device
+// memory (BInst, BState), so the launch arguments stay fixed while
+// instances come and go, and a captured graph of steps can be replayed.
+
+// What the kernels read about one instance.
+struct BInst {
+    void* f[2];  // state buffers; f[t & 1] holds f*(t)
+    const uint8_t* flags;
+    const void* psiw;
+    const int* side_idx;
+    double* side_mom;
+    double* side_f;
+    double* partial;  // one FP64 mass partial per tile
+    int nx, ny, pitch, nsegs, nstrips, np;
+    long long plane;
+    Phys<double> ph;
+    // boundary tables (see BndArgs)
+    int nslot, fix;
+    const int *lnode, *lmeta, *lghost, *lxf, *lxff, *lslotb, *lslotf;
+    const double *lc, *luw;
+    double rref;
+    double* hist;
+    long long cap;
+    long long* unstable;
+};
+
+// Time step of an instance and the steps it still has to run; an instance
+// with remaining <= 0 is skipped by every launch.
+struct BState {
+    long long t;
+    long long remaining;
+};
+
+struct BatchArgs {
+    const BInst* __restrict__ inst;
+    BState* __restrict__ state;
+    const int2* __restrict__ tiles;  // (instance, tile) in queue order
+    int* __restrict__ qnext;         // [8] queue heads, zeroed by the reduce pass
+    const int* __restrict__ qbound;  // [9]: queue k holds tiles [qbound[k], qbound[k+1])
+    const int2* __restrict__ lblk;   // (instance, link block)
+    const int* __restrict__ nlblk;   // number of link blocks
+    int ninst;                       // instance slots
+    int tile_h;
+    int persistent;                  // 1: tile queues, 0: one workgroup per tile
+};
+
+template <typename S>
+__device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long t, int tile_h) {
+    MainArgs<S> a;
+    const int c = int(t & 1);
+    a.src = static_cast<const S*>(I.f[c]);
+    a.dst = static_cast<S*>(I.f[c ^ 1]);
+    a.flags = I.flags;
+    a.psiw = I.psiw;
+    a.side_idx = I.side_idx;
+    a.side_mom = I.side_mom;
+    a.side_f = I.side_f;
+    a.partial = I.partial;
+    a.mom_out = nullptr;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.pitch = I.pitch;
+    a.plane = I.plane;
+    a.tile_h = tile_h;
+    a.nsegs = I.nsegs;
+    a.nstrips = I.nstrips;
+    return a;
+}
+
+template <typename S, typename R, int EOS, bool DEV>
+__device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
+    g = __builtin_amdgcn_readfirstlane(g);
+    const int2 te = b.tiles[g];
+    const BState st = b.state[te.x];
+    if (st.remaining <= 0) return;
+    const BInst& I = b.inst[te.x];
+    main_tile<S, R, EOS, false, DEV>(inst_main_args<S>(I, st.t, b.tile_h), phys_as<R>(I.ph),
+                                     te.y);
+}
+
+// Persistent form: a fixed grid; each workgroup takes tiles from the queue
+// of its XCD (workgroups are dispatched to the XCDs round robin), then from
+// the other queues in turn, until all are empty.  The queues hold
+// contiguous runs of the tile list, so one XCD works through compact
+// pieces of the same instances and finds their halos in its L2.
+template <typename S, typename R, int EOS, bool DEV>
+__global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
+    if (!b.persistent) {
+        batch_tile<S, R, EOS, DEV>(b, xcd_tile(blockIdx.x, gridDim.x));
+        return;
+    }
+    __shared__ int s_g;
+    const int xcd = blockIdx.x & 7;
+    int qi = 0;
+    for (;;) {
+        __syncthreads();  // the previous tile is done with s_g and the LDS ring
+        if (threadIdx.x == 0) {
+            int g = -1;
+            while (qi < 8) {
+                const int q = (xcd + qi) & 7;
+                const int k = b.qbound[q] + atomicAdd(&b.qnext[q], 1);
+                if (k < b.qbound[q + 1]) {
+                    g = k;
+                    break;
+                }
+                ++qi;
+            }
+            s_g = g;
+        }
+        __syncthreads();
+        const int g = s_g;
+        if (g < 0) break;
+        batch_tile<S, R, EOS, DEV>(b, g);
+    }
+}
+
+template <typename S, bool DEV>
+__global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
+    const int n = *b.nlblk;
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+        const int2 e = b.lblk[k];
+        const BState st = b.state[e.x];
+        if (st.remaining <= 0) continue;
+        const BInst& I = b.inst[e.x];
+        BndArgs a;
+        a.nslot = I.nslot;
+        a.lnode = I.lnode;
+        a.lmeta = I.lmeta;
+        a.lghost = I.lghost;
+        a.lxf = I.lxf;
+        a.lxff = I.lxff;
+        a.lslotb = I.lslotb;
+        a.lslotf = I.lslotf;
+        a.lc = I.lc;
+        a.luw = I.luw;
+        a.side_mom = I.side_mom;
+        a.side_f = I.side_f;
+        a.plane = I.plane;
+        a.rref = I.rref;
+        a.fix = I.fix;
+        a.partial = nullptr;
+        a.np = 0;
+        a.hist = nullptr;
+        a.slot = 0;
+        a.t = 0;
+        a.unstable = nullptr;
+        a.do_reduce = 0;
+        __syncthreads();  // the previous block is done with the LDS
+        boundary_block<S, DEV>(static_cast<S*>(I.f[st.t & 1]), a, e.y);
+    }
+}
+
+// Per instance: M(t+1) from the main pass's partials in a fixed order, the
+// first non-finite mass, t += 1 and one step fewer to run (none once
+// unstable).  Also empties the tile queues for the next main pass.
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
+    for (int i = blockIdx.x; i < b.ninst; i += gridDim.x) {
+        BState* st = b.state + i;
+        const long long rem = st->remaining;
+        if (rem <= 0) continue;
+        const BInst& I = b.inst[i];
+        const long long t1 = st->t + 1;
+        __syncthreads();
+        reduce_partials(I.partial, I.np, I.hist, t1 % I.cap, t1, I.unstable);
+        if (threadIdx.x == 0) {
+            st->t = t1;
+            st->remaining = *I.unstable >= 0 ? 0 : rem - 1;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 8) b.qnext[threadIdx.x] = 0;
 }
 
 }  // namespace lbm

@@ -53,6 +53,22 @@ struct Phys {
     R s[9];        // relaxation rates of the nine moments (BGK: all 1/tau)
 };
 
+template <typename R>
+__host__ __device__ __forceinline__ Phys<R> phys_as(const Phys<double>& d) {
+    Phys<R> p;
+    p.G = R(d.G);
+    p.gx = R(d.gx);
+    p.gy = R(d.gy);
+    p.e0 = R(d.e0);
+    p.e1 = R(d.e1);
+    p.e2 = R(d.e2);
+    p.e3 = R(d.e3);
+    p.p2G = R(d.p2G);
+    p.rref = R(d.rref);
+    for (int i = 0; i < 9; ++i) p.s[i] = R(d.s[i]);
+    return p;
+}
+
 enum { EOS_NONE = 0, EOS_EXP = 1, EOS_CS = 2 };
 
 // Reciprocal and square root: correctly rounded in FP64; the hardware

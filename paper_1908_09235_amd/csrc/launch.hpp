@@ -40,4 +40,22 @@ void launch_init_f32(const Ctx& c, const double* rho_wall, const double* rho0,
 void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
                    long long* unstable);
 
+// One step of a batch: boundary and main passes (per storage precision),
+// then the per-instance reduction.
+struct BatchLaunch {
+    BatchArgs args;
+    int eos, storage;
+    int tile_w;     // main-pass workgroup size
+    int main_grid;  // persistent: workgroups; otherwise: tiles
+    int bnd_grid;
+    int red_grid;
+    hipStream_t stream;
+};
+void launch_batch_f64(const BatchLaunch& L);
+void launch_batch_f32(const BatchLaunch& L);
+void launch_batch_reduce(const BatchLaunch& L);
+// resident workgroups per CU of the batched main kernel
+int batch_occupancy_f64(int eos, int storage, int tile_w);
+int batch_occupancy_f32(int eos, int storage, int tile_w);
+
 }  // namespace lbm

@@ -30,4 +30,21 @@ void launch_init_f32(const Ctx& c, const double* rw, const double* r0, const dou
     }
 }
 
+void launch_batch_f32(const BatchLaunch& L) {
+    switch (L.storage) {
+    case 2: batch_any<float, float, false>(L); break;
+    case 3: batch_any<float, float, true>(L); break;
+    case 4: batch_any<_Float16, float, true>(L); break;
+    default: batch_any<float, double, false>(L);
+    }
+}
+int batch_occupancy_f32(int eos, int storage, int tile_w) {
+    switch (storage) {
+    case 2: return occupancy_any<float, float, false>(eos, tile_w);
+    case 3: return occupancy_any<float, float, true>(eos, tile_w);
+    case 4: return occupancy_any<_Float16, float, true>(eos, tile_w);
+    default: return occupancy_any<float, double, false>(eos, tile_w);
+    }
+}
+
 }  // namespace lbm

@@ -7,18 +7,7 @@ namespace lbm {
 
 template <typename R>
 Phys<R> convert(const Phys<double>& d) {
-    Phys<R> p;
-    p.G = R(d.G);
-    p.gx = R(d.gx);
-    p.gy = R(d.gy);
-    p.e0 = R(d.e0);
-    p.e1 = R(d.e1);
-    p.e2 = R(d.e2);
-    p.e3 = R(d.e3);
-    p.p2G = R(d.p2G);
-    p.rref = R(d.rref);
-    for (int i = 0; i < 9; ++i) p.s[i] = R(d.s[i]);
-    return p;
+    return phys_as<R>(d);
 }
 
 template <typename S, typename R, int EOS, bool MOM, bool DEV>
@@ -82,6 +71,37 @@ void init_any(const Ctx& c, const double* rw, const double* r0, const double* u0
                            c.flags, c.nx, c.ny, c.pitch, ph);
     hipLaunchKernelGGL(k_init_scatter<S>, g, dim3(256), 0, c.stream, static_cast<S*>(buf),
                        c.flags, r0, u0, v0, c.nx, c.ny, c.pitch, c.plane, c.ph.rref);
+}
+
+template <typename S, typename R, bool DEV>
+void batch_any(const BatchLaunch& L) {
+    hipLaunchKernelGGL((k_boundary_batch<S, DEV>), dim3(L.bnd_grid), dim3(256), 0, L.stream,
+                       L.args);
+    if (L.eos == EOS_EXP)
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_EXP, DEV>), dim3(L.main_grid),
+                           dim3(L.tile_w), 0, L.stream, L.args);
+    else if (L.eos == EOS_CS)
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_CS, DEV>), dim3(L.main_grid),
+                           dim3(L.tile_w), 0, L.stream, L.args);
+    else
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_NONE, DEV>), dim3(L.main_grid),
+                           dim3(L.tile_w), 0, L.stream, L.args);
+}
+
+template <typename S, typename R, bool DEV>
+int occupancy_any(int eos, int tile_w) {
+    int n = 0;
+    hipError_t e;
+    if (eos == EOS_EXP)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_EXP, DEV>), tile_w, 0);
+    else if (eos == EOS_CS)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_CS, DEV>), tile_w, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_NONE, DEV>), tile_w, 0);
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace lbm

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/lbm2p.h"
+#include "domain.hpp"
 #include "launch.hpp"
 
 using namespace lbm;
@@ -21,51 +22,14 @@ constexpr int kProfPool = 1024;
 
 }  // namespace
 
-struct lbm_domain {
-    int nx = 0, ny = 0, pitch = 0;
-    long long plane = 0;
-    int storage = 0, eos = 0, coll = 0, rule = 0, fix = 0;
-    int tile_w = 0, tile_h = 0, nstrips = 0, nsegs = 0, nblocks = 0;
-    size_t esize = 8;
-    void* f[2] = {nullptr, nullptr};
-    int cur = 0;
-    uint8_t* flags = nullptr;
-    void* psiw = nullptr;
-    int* side_idx = nullptr;
-    double* side_mom = nullptr;
-    double* side_f = nullptr;
-    int nslots = 0;
-    bool save_f = false;
-    double* partial = nullptr;
-    double* hist = nullptr;
-    long long* unstable = nullptr;
-    double* mom_out = nullptr;
-    int nb = 0, nl = 0;
-    int nslot_links = 0;
-    int *lnode = nullptr, *lmeta = nullptr, *lghost = nullptr, *lxf = nullptr,
-        *lxff = nullptr, *lslotb = nullptr, *lslotf = nullptr;
-    double *lc = nullptr, *luw = nullptr;
-    long long cap = 0, t = 0;
-    bool pending = false;
-    long long pending_t = 0;
-    hipStream_t stream = nullptr;
-    Phys<double> ph64{};
-    Phys<float> ph32{};
-    size_t bytes = 0;
-    long long fluid = 0, fallbacks = 0;
-    std::vector<void*> allocs;
-    int prof = 0;  // record every prof-th step (0: off)
-    int nrec = 0;
-    std::vector<hipEvent_t> ev;
-    double main_ms = 0, bnd_ms = 0;
-    long long main_n = 0, bnd_n = 0;
-};
-
 namespace {
 
 int dev_alloc(lbm_domain* d, void** p, size_t bytes) {
     if (bytes == 0) bytes = 8;
-    if (hipMalloc(p, bytes) != hipSuccess) {
+    if (d->arena) {
+        *p = d->arena->alloc(bytes);
+        if (!*p) return LBM_ENOMEM;
+    } else if (hipMalloc(p, bytes) != hipSuccess) {
         *p = nullptr;
         return LBM_ENOMEM;
     }
@@ -74,19 +38,33 @@ int dev_alloc(lbm_domain* d, void** p, size_t bytes) {
     return LBM_OK;
 }
 
+void dev_free(lbm_domain* d, void* p, size_t bytes) {
+    if (d->arena) d->arena->release(p);
+    else (void)hipFree(p);
+    d->allocs.erase(std::find(d->allocs.begin(), d->allocs.end(), p));
+    d->bytes -= bytes;
+}
+
+// host vectors stay alive until the creating call synchronises the stream
 template <typename T>
 int upload(lbm_domain* d, T** dst, const std::vector<T>& src) {
     int rc = dev_alloc(d, reinterpret_cast<void**>(dst), src.size() * sizeof(T));
     if (rc) return rc;
-    if (!src.empty() &&
-        hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    if (!src.empty() && hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T),
+                                       hipMemcpyHostToDevice, d->stream) != hipSuccess)
         return LBM_EDEVICE;
     return LBM_OK;
 }
 
 void free_domain(lbm_domain* d) {
     if (!d) return;
-    for (void* p : d->allocs) (void)hipFree(p);
+    // queued work on the domain's stream may still use the memory
+    (void)hipStreamSynchronize(d->stream);
+    if (d->arena) {
+        for (void* p : d->allocs) d->arena->release(p);
+    } else {
+        for (void* p : d->allocs) (void)hipFree(p);
+    }
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
     delete d;
 }
@@ -528,8 +506,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     const size_t fbytes = (size_t)9 * d->plane * d->esize;
     if ((rc = dev_alloc(d, &d->f[0], fbytes))) return rc;
     if ((rc = dev_alloc(d, &d->f[1], fbytes))) return rc;
-    if (hipMemset(d->f[0], 0, fbytes) != hipSuccess) return LBM_EDEVICE;
-    if (hipMemset(d->f[1], 0, fbytes) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemsetAsync(d->f[0], 0, fbytes, d->stream) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemsetAsync(d->f[1], 0, fbytes, d->stream) != hipSuccess) return LBM_EDEVICE;
     if ((rc = upload(d, &d->flags, flags))) return rc;
     if ((rc = upload(d, &d->side_idx, side_idx))) return rc;
     if ((rc = dev_alloc(d, &d->psiw, (size_t)P * ny * 8))) return rc;
@@ -537,9 +515,14 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = dev_alloc(d, (void**)&d->side_f,
                         (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8)))
         return rc;
-    if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->nblocks * 8))) return rc;
+    // partials for any tile shape down to 64 x 8 (the batched form retunes)
+    d->partial_cap = std::max(d->nblocks, ((nx + 63) / 64) * ((ny + 7) / 8));
+    if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->partial_cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
+    // in an arena (batched and served instances) the read-out buffer is part
+    // of the footprint, so that reading a finished instance never fails
+    if (d->arena && (rc = dev_alloc(d, (void**)&d->mom_out, (size_t)3 * N * 8))) return rc;
     if ((rc = upload(d, &d->lnode, lnode))) return rc;
     if ((rc = upload(d, &d->lmeta, lmeta))) return rc;
     if ((rc = upload(d, &d->lghost, lghost))) return rc;
@@ -550,8 +533,10 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &d->lc, lc))) return rc;
     if ((rc = upload(d, &d->luw, luw))) return rc;
     const long long minus1 = -1;
-    if (hipMemcpy(d->unstable, &minus1, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
-    if (hipMemset(d->hist, 0, (size_t)d->cap * 8) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    if (hipMemsetAsync(d->hist, 0, (size_t)d->cap * 8, d->stream) != hipSuccess)
+        return LBM_EDEVICE;
 
     // ---- initial state: psi at walls, f(0) scattered, f*(0) by one main pass
     std::vector<double> rw((size_t)N), r0((size_t)N), u0((size_t)N, 0.0), v0((size_t)N, 0.0);
@@ -577,22 +562,19 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
     // the initial fields are no longer needed
-    for (double* p : {drw, dr0, du0, dv0}) {
-        (void)hipFree(p);
-        d->allocs.erase(std::find(d->allocs.begin(), d->allocs.end(), (void*)p));
-        d->bytes -= (size_t)N * 8;
-    }
+    for (double* p : {drw, dr0, du0, dv0}) dev_free(d, p, (size_t)N * 8);
     return check_unstable(d);
 }
 
 }  // namespace
 
-extern "C" {
+namespace lbm {
 
-int lbm_create_domain(const lbm_desc* desc, lbm_domain** out) {
+int domain_create(const lbm_desc* desc, Arena* arena, lbm_domain** out) {
     if (!desc || !out) return LBM_EINVAL;
     lbm_domain* d = new (std::nothrow) lbm_domain();
     if (!d) return LBM_ENOMEM;
+    d->arena = arena;
     int rc = validate_and_build(desc, d);
     if (rc != LBM_OK) {
         free_domain(d);
@@ -600,6 +582,91 @@ int lbm_create_domain(const lbm_desc* desc, lbm_domain** out) {
     }
     *out = d;
     return LBM_OK;
+}
+
+void domain_free(lbm_domain* d) { free_domain(d); }
+
+int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h) {
+    if (tile_w != 64 && tile_w != 128 && tile_w != 256) return LBM_EINVAL;
+    if (tile_h < 1) return LBM_EINVAL;
+    const int ns = (d->nx + tile_w - 1) / tile_w, ng = (d->ny + tile_h - 1) / tile_h;
+    if ((long long)ns * ng > d->partial_cap) return LBM_EINVAL;
+    d->tile_w = tile_w;
+    d->tile_h = tile_h;
+    d->nstrips = ns;
+    d->nsegs = ng;
+    d->nblocks = ns * ng;
+    return LBM_OK;
+}
+
+Ctx domain_ctx(lbm_domain* d) { return ctx(d); }
+
+// ------------------------------------------------------------------ arena
+Arena::~Arena() {
+    if (base_) (void)hipFree(base_);
+}
+
+int Arena::init(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0 || hipMalloc(reinterpret_cast<void**>(&base_), bytes) != hipSuccess) {
+        base_ = nullptr;
+        return LBM_ENOMEM;
+    }
+    cap_ = bytes;
+    free_[0] = bytes;
+    return LBM_OK;
+}
+
+void* Arena::alloc(size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        live_[off] = bytes;
+        used_ += bytes;
+        return base_ + off;
+    }
+    return nullptr;
+}
+
+void Arena::release(void* p) {
+    if (!p) return;
+    const size_t off = static_cast<size_t>(static_cast<char*>(p) - base_);
+    auto lv = live_.find(off);
+    if (lv == live_.end()) return;
+    size_t start = off, len = lv->second;
+    live_.erase(lv);
+    used_ -= len;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + len) {  // merge with the next block
+        len += nx->second;
+        nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {  // and with the previous one
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == start) {
+            start = pv->first;
+            len += pv->second;
+            free_.erase(pv);
+        }
+    }
+    free_[start] = len;
+}
+
+size_t Arena::largest_free() const {
+    size_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+}
+
+}  // namespace lbm
+
+extern "C" {
+
+int lbm_create_domain(const lbm_desc* desc, lbm_domain** out) {
+    return domain_create(desc, nullptr, out);
 }
 
 int lbm_step_async(lbm_domain* d, int64_t n) {

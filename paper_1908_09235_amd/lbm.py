@@ -53,6 +53,14 @@ class lbm_desc(C.Structure):
                 ("rho_ref", C.c_double)]
 
 
+class lbm_batch_desc(C.Structure):
+    _fields_ = [("storage", C.c_int32), ("eos", C.c_int32),
+                ("max_instances", C.c_int32), ("tile_w", C.c_int32),
+                ("tile_h", C.c_int32), ("persistent", C.c_int32),
+                ("graph_steps", C.c_int32), ("reserved", C.c_int32),
+                ("arena_bytes", C.c_int64), ("stream", C.c_void_p)]
+
+
 assert C.sizeof(lbm_link) == 40 and LINK_NP.itemsize == 40
 
 _D = C.POINTER(C.c_double)
@@ -78,6 +86,29 @@ EXPORTS = {
     "lbm_info": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_destroy": (None, [_H]),
     "lbm_status_string": (C.c_char_p, [C.c_int]),
+    "lbm_batch_create": (C.c_int, [C.POINTER(lbm_batch_desc), C.POINTER(_H)]),
+    "lbm_batch_add": (C.c_int, [_H, C.POINTER(lbm_desc), C.c_int64, C.POINTER(C.c_int32)]),
+    "lbm_batch_run": (C.c_int, [_H, C.c_int64]),
+    "lbm_batch_sync": (C.c_int, [_H]),
+    "lbm_batch_status": (C.c_int, [_H, C.c_int32, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "lbm_batch_moments": (C.c_int, [_H, C.c_int32, _D, _D, _D]),
+    "lbm_batch_mass_history": (C.c_int, [_H, C.c_int32, _D, C.c_int64,
+                                         C.POINTER(C.c_int64)]),
+    "lbm_batch_remove": (C.c_int, [_H, C.c_int32]),
+    "lbm_batch_tune": (C.c_int, [_H, C.c_int64, C.POINTER(C.c_int32)]),
+    "lbm_batch_info": (C.c_int, [_H, C.POINTER(C.c_int64)]),
+    "lbm_batch_destroy": (None, [_H]),
+    "lbm_server_create": (C.c_int, [C.POINTER(lbm_batch_desc), C.c_int64, C.POINTER(_H)]),
+    "lbm_server_submit": (C.c_int, [_H, C.POINTER(lbm_desc), C.c_int64,
+                                    C.POINTER(C.c_int64)]),
+    "lbm_server_progress": (C.c_int, [_H, C.POINTER(C.c_int64), C.c_int64,
+                                      C.POINTER(C.c_int64)]),
+    "lbm_server_result": (C.c_int, [_H, C.c_int64, _D, _D, _D, _D, C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)]),
+    "lbm_server_release": (C.c_int, [_H, C.c_int64]),
+    "lbm_server_info": (C.c_int, [_H, C.POINTER(C.c_int64)]),
+    "lbm_server_destroy": (None, [_H]),
 }
 
 
@@ -288,6 +319,258 @@ class Domain:
         if getattr(self, "h", None) is not None and self.h.value:
             lbm_destroy(self.h)
             self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batches
+def make_batch_desc(storage="f32", eos="cs", max_instances=1024, tile_w=0, tile_h=0,
+                    persistent=1, graph_steps=0, arena_bytes=1 << 30, stream=None):
+    bd = lbm_batch_desc()
+    bd.storage = STORAGE[storage]
+    bd.eos = EOS[eos]
+    bd.max_instances = max_instances
+    bd.tile_w, bd.tile_h = tile_w, tile_h
+    bd.persistent = persistent
+    bd.graph_steps = graph_steps
+    bd.reserved = 0
+    bd.arena_bytes = int(arena_bytes)
+    bd.stream = stream
+    return bd
+
+
+def lbm_batch_create(**kw):
+    bd = make_batch_desc(**kw)
+    h = _H()
+    _check(lib().lbm_batch_create(C.byref(bd), C.byref(h)), "lbm_batch_create")
+    return h
+
+
+def lbm_batch_add(h, problem, steps, storage="f32", history_capacity=0, rho_ref=0.0):
+    d, keep = make_desc(problem, storage, 0, 0, None, history_capacity, rho_ref)
+    slot = C.c_int32()
+    _check(lib().lbm_batch_add(h, C.byref(d), int(steps), C.byref(slot)), "lbm_batch_add")
+    del keep
+    return slot.value
+
+
+def lbm_batch_run(h, n):
+    _check(lib().lbm_batch_run(h, int(n)), "lbm_batch_run")
+
+
+def lbm_batch_sync(h):
+    _check(lib().lbm_batch_sync(h), "lbm_batch_sync")
+
+
+def lbm_batch_status(h, slot):
+    t, r, u = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().lbm_batch_status(h, int(slot), C.byref(t), C.byref(r), C.byref(u)),
+           "lbm_batch_status")
+    return t.value, r.value, u.value
+
+
+def lbm_batch_moments(h, slot, nx, ny):
+    r, ux, uy = (np.zeros((ny, nx)) for _ in range(3))
+    _check(lib().lbm_batch_moments(h, int(slot), _dptr(r), _dptr(ux), _dptr(uy)),
+           "lbm_batch_moments")
+    return r, ux, uy
+
+
+def lbm_batch_mass_history(h, slot, cap):
+    out = np.zeros(max(int(cap), 1))
+    n = C.c_int64()
+    _check(lib().lbm_batch_mass_history(h, int(slot), _dptr(out), int(cap), C.byref(n)),
+           "lbm_batch_mass_history")
+    return out[:n.value]
+
+
+def lbm_batch_remove(h, slot):
+    _check(lib().lbm_batch_remove(h, int(slot)), "lbm_batch_remove")
+
+
+def lbm_batch_tune(h, steps_per_trial):
+    out = (C.c_int32 * 4)()
+    _check(lib().lbm_batch_tune(h, int(steps_per_trial), out), "lbm_batch_tune")
+    return {"tile_w": out[0], "tile_h": out[1], "persistent": out[2], "us_per_step": out[3]}
+
+
+def lbm_batch_info(h):
+    out = (C.c_int64 * 8)()
+    _check(lib().lbm_batch_info(h, out), "lbm_batch_info")
+    keys = ("instances", "tiles", "link_blocks", "arena_bytes", "arena_used", "tile_w",
+            "tile_h", "persistent")
+    return dict(zip(keys, list(out)))
+
+
+def lbm_batch_destroy(h):
+    lib().lbm_batch_destroy(h)
+
+
+class Batch:
+    """Owning wrapper around an lbm_batch handle."""
+
+    def __init__(self, storage="f32", eos="cs", **kw):
+        self.storage = storage
+        self.h = lbm_batch_create(storage=storage, eos=eos, **kw)
+        self.shape = {}
+
+    def add(self, problem, steps, history_capacity=0, rho_ref=0.0):
+        s = lbm_batch_add(self.h, problem, steps, self.storage, history_capacity, rho_ref)
+        self.shape[s] = (problem.nx, problem.ny)
+        return s
+
+    def run(self, n):
+        lbm_batch_run(self.h, n)
+
+    def sync(self):
+        lbm_batch_sync(self.h)
+
+    def status(self, slot):
+        return lbm_batch_status(self.h, slot)
+
+    def moments(self, slot):
+        nx, ny = self.shape[slot]
+        return lbm_batch_moments(self.h, slot, nx, ny)
+
+    def mass_history(self, slot):
+        t = self.status(slot)[0]
+        return lbm_batch_mass_history(self.h, slot, t + 1)
+
+    def remove(self, slot):
+        lbm_batch_remove(self.h, slot)
+        self.shape.pop(slot, None)
+
+    def tune(self, steps_per_trial):
+        return lbm_batch_tune(self.h, steps_per_trial)
+
+    def info(self):
+        return lbm_batch_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- server
+def lbm_server_create(chunk_steps, **kw):
+    bd = make_batch_desc(**kw)
+    h = _H()
+    _check(lib().lbm_server_create(C.byref(bd), int(chunk_steps), C.byref(h)),
+           "lbm_server_create")
+    return h
+
+
+def lbm_server_submit(h, desc, steps):
+    i = C.c_int64()
+    _check(lib().lbm_server_submit(h, C.byref(desc), int(steps), C.byref(i)),
+           "lbm_server_submit")
+    return i.value
+
+
+def lbm_server_progress(h, cap=4096):
+    ids = (C.c_int64 * max(int(cap), 1))()
+    n = C.c_int64()
+    _check(lib().lbm_server_progress(h, ids, int(cap), C.byref(n)), "lbm_server_progress")
+    return list(ids[:n.value])
+
+
+def lbm_server_result(h, rid, nx=None, ny=None, fields=True):
+    m = (C.c_double * 2)()
+    steps, u = C.c_int64(), C.c_int64()
+    if fields:
+        r, ux, uy = (np.zeros((ny, nx)) for _ in range(3))
+        ptrs = (_dptr(r), _dptr(ux), _dptr(uy))
+    else:
+        r = ux = uy = None
+        ptrs = (None, None, None)
+    _check(lib().lbm_server_result(h, int(rid), *ptrs, m, C.byref(steps), C.byref(u)),
+           "lbm_server_result")
+    return {"rho": r, "ux": ux, "uy": uy, "mass0": m[0], "mass": m[1],
+            "steps": steps.value, "unstable_step": u.value}
+
+
+def lbm_server_release(h, rid):
+    _check(lib().lbm_server_release(h, int(rid)), "lbm_server_release")
+
+
+def lbm_server_info(h):
+    out = (C.c_int64 * 8)()
+    _check(lib().lbm_server_info(h, out), "lbm_server_info")
+    keys = ("queued", "running", "finished", "arena_used", "arena_bytes", "chunks",
+            "admitted", "rejected")
+    return dict(zip(keys, list(out)))
+
+
+def lbm_server_destroy(h):
+    lib().lbm_server_destroy(h)
+
+
+class Server:
+    """Owning wrapper around an lbm_server handle.  Submitted problems are
+    kept alive here until they are admitted."""
+
+    def __init__(self, chunk_steps=64, storage="f32", eos="cs", **kw):
+        self.storage = storage
+        self.h = lbm_server_create(chunk_steps, storage=storage, eos=eos, **kw)
+        self.keep = {}
+        self.shape = {}
+
+    def submit(self, problem, steps, history_capacity=0, rho_ref=0.0):
+        d, keep = make_desc(problem, self.storage, 0, 0, None, history_capacity, rho_ref)
+        rid = lbm_server_submit(self.h, d, steps)
+        self.keep[rid] = (d, keep)
+        self.shape[rid] = (problem.nx, problem.ny)
+        return rid
+
+    def progress(self):
+        done = lbm_server_progress(self.h)
+        # requests leave the queue in id order: the first admitted + rejected
+        # ids no longer need their arrays
+        info = self.info()
+        gone = info["admitted"] + info["rejected"]
+        for rid in [r for r in self.keep if r < gone]:
+            del self.keep[rid]
+        return done
+
+    def result(self, rid, fields=True):
+        nx, ny = self.shape[rid]
+        return lbm_server_result(self.h, rid, nx, ny, fields)
+
+    def release(self, rid):
+        lbm_server_release(self.h, rid)
+        self.shape.pop(rid, None)
+
+    def info(self):
+        return lbm_server_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lbm_server_destroy(self.h)
+            self.h = None
+        self.keep = {}
 
     def __enter__(self):
         return self

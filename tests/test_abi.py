@@ -124,7 +124,7 @@ def test_bad_launch_shape_and_storage_are_rejected(L):
 
 
 def test_binding_struct_layout_matches_header(L, tmp_path):
-    """The ctypes mirrors of lbm_desc and lbm_link have the header's field
+    """The ctypes mirrors of the header's structs have its field
     offsets and sizes (a C program built from the header prints them)."""
     import shutil
     import subprocess
@@ -135,7 +135,9 @@ def test_binding_struct_layout_matches_header(L, tmp_path):
     inc = Path(__file__).resolve().parents[1] / "include"
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm2p.h"',
              'int main(void) {']
-    for st, cls in (("lbm_desc", L.lbm_desc), ("lbm_link", L.lbm_link)):
+    structs = (("lbm_desc", L.lbm_desc), ("lbm_link", L.lbm_link),
+               ("lbm_batch_desc", L.lbm_batch_desc))
+    for st, cls in structs:
         lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
         for name, _ in cls._fields_:
             lines.append(f'printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
@@ -149,7 +151,32 @@ def test_binding_struct_layout_matches_header(L, tmp_path):
     for line in out.splitlines():
         st, name, val = line.split()
         got[(st, name)] = int(val)
-    for st, cls in (("lbm_desc", L.lbm_desc), ("lbm_link", L.lbm_link)):
+    for st, cls in structs:
         assert got[(st, "sizeof")] == ctypes.sizeof(cls), st
         for name, _ in cls._fields_:
             assert got[(st, name)] == getattr(cls, name).offset, (st, name)
+
+
+def test_batch_descriptors_are_validated(L):
+    """lbm_batch_create and lbm_server_create reject bad fields before any
+    device call."""
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    good = dict(storage="f32", eos="cs", max_instances=4, arena_bytes=1 << 20)
+    for bad in (dict(max_instances=0), dict(tile_w=96), dict(tile_h=4), dict(persistent=2),
+                dict(arena_bytes=0)):
+        bd = L.make_batch_desc(**{**good, **bad})
+        assert lib.lbm_batch_create(ctypes.byref(bd), ctypes.byref(h)) == L.LBM_EINVAL, bad
+    for field, val in (("storage", 9), ("eos", 3), ("reserved", 1)):
+        bd = L.make_batch_desc(**good)
+        setattr(bd, field, val)
+        assert lib.lbm_batch_create(ctypes.byref(bd), ctypes.byref(h)) == L.LBM_EINVAL, field
+    bd = L.make_batch_desc(**good)
+    assert lib.lbm_server_create(ctypes.byref(bd), 0, ctypes.byref(h)) == L.LBM_EINVAL
+    assert lib.lbm_batch_create(None, ctypes.byref(h)) == L.LBM_EINVAL
+    for fn, args in (("lbm_batch_run", (None, 1)), ("lbm_batch_sync", (None,)),
+                     ("lbm_batch_remove", (None, 0)), ("lbm_batch_info", (None, None)),
+                     ("lbm_batch_add", (None, None, 1, None)),
+                     ("lbm_server_progress", (None, None, 0, None)),
+                     ("lbm_server_release", (None, 0)), ("lbm_server_info", (None, None))):
+        assert getattr(lib, fn)(*args) == L.LBM_EINVAL, fn

@@ -1,0 +1,247 @@
+"""Batched and served forms against the same instances run alone.
+
+Every instance of a batch computes exactly what lbm_step computes for it
+alone, with the same main-pass tile shape: rho, u and the mass history must
+agree bit for bit.  The FP32 batch is also held to 1e-5 of the FP64 form
+(the gate of the batched workload), and the served form must give each
+request the result it gets alone, whatever else is in the mix."""
+import sys
+
+import numpy as np
+import pytest
+
+from lbm_inputs import configs as cfg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_09235_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+def small_mix(n, lo=64, hi=160, seed=4):
+    return [cfg.batch_instance(k, seed=seed, side_lo=lo, side_hi=hi) for k in range(n)]
+
+
+def alone(L, p, steps, storage, tile_w=256, tile_h=16):
+    with L.Domain(p, storage=storage, tile_w=tile_w, tile_h=tile_h,
+                  history_capacity=4096) as d:
+        try:
+            d.step(steps)
+        except L.LbmError as e:
+            if e.code != L.LBM_EUNSTABLE:
+                raise
+        r = d.moments()
+        h = d.mass_history()
+        u = L.lbm_unstable_step(d.h)
+    return r, h, u
+
+
+def same(a, b):
+    return all(np.array_equal(x, y, equal_nan=True) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("storage,persistent,graph", [
+    ("f64", 1, 0), ("f64", 0, 8), ("f32", 1, 8), ("f32dev", 1, 0), ("f16dev", 0, 0)])
+def test_batch_equals_alone(L, storage, persistent, graph):
+    probs = small_mix(6)
+    steps = 120
+    say(f"[gpu] batch {storage} persistent={persistent} graph={graph} sides "
+        f"{[p.nx for p in probs]}")
+    with L.Batch(storage=storage, eos="cs", max_instances=16, tile_w=128, tile_h=16,
+                 persistent=persistent, graph_steps=graph, arena_bytes=1 << 30) as b:
+        slots = [b.add(p, steps, history_capacity=4096) for p in probs]
+        b.run(steps + 7)  # instances stop at their own count
+        for s, p in zip(slots, probs):
+            t, rem, u = b.status(s)
+            g = b.moments(s)
+            h = b.mass_history(s)
+            # an unstable instance stops at its first non-finite mass
+            a_mom, a_hist, a_u = alone(L, p, steps if u < 0 else u, storage, 128, 16)
+            say(f"    {p.name} side {p.nx} tau {p.tau:.3f}: t={t} unstable={u}")
+            assert rem == 0 and u == a_u
+            assert t == (steps if u < 0 else u)
+            assert same(g, a_mom)
+            assert np.array_equal(h, a_hist, equal_nan=True)
+
+
+def test_steps_per_instance_and_slot_reuse(L):
+    probs = small_mix(3)
+    with L.Batch(storage="f64", eos="cs", max_instances=3, tile_w=64, tile_h=8,
+                 arena_bytes=1 << 29) as b:
+        s = [b.add(p, n, history_capacity=512) for p, n in zip(probs, (10, 25, 40))]
+        b.run(30)
+        assert [b.status(k)[0] for k in s] == [10, 25, 30]
+        assert [b.status(k)[1] for k in s] == [0, 0, 10]
+        # a full batch refuses more; removing frees the slot
+        q = cfg.batch_instance(7, side_lo=64, side_hi=160)
+        with pytest.raises(L.LbmError) as e:
+            b.add(q, 5)
+        assert e.value.code == L.LBM_ENOMEM
+        b.remove(s[0])
+        s3 = b.add(q, 20, history_capacity=512)
+        b.run(20)
+        assert b.status(s3)[0] == 20 and b.status(s[2])[0] == 40
+        assert same(b.moments(s3), alone(L, q, 20, "f64", 64, 8)[0])
+        assert same(b.moments(s[2]), alone(L, probs[2], 40, "f64", 64, 8)[0])
+
+
+def test_arena_admission_limit(L):
+    """An instance that does not fit the arena is refused with ENOMEM and
+    leaves the batch usable."""
+    big = cfg.batch_instance(0, side_lo=700, side_hi=768)
+    small = cfg.batch_instance(1, side_lo=64, side_hi=80)
+    with L.Batch(storage="f32", eos="cs", max_instances=4, arena_bytes=8 << 20) as b:
+        with pytest.raises(L.LbmError) as e:
+            b.add(big, 5)
+        assert e.value.code == L.LBM_ENOMEM
+        k = b.add(small, 5, history_capacity=64)
+        b.run(5)
+        assert b.status(k)[0] == 5
+        info = b.info()
+        assert info["instances"] == 1 and info["arena_used"] <= info["arena_bytes"]
+
+
+def test_autotuner_keeps_results(L):
+    probs = small_mix(5, 64, 300)
+    steps = 3 * 18 * 2 + 40
+    with L.Batch(storage="f64", eos="cs", max_instances=8, arena_bytes=1 << 30) as b:
+        slots = [b.add(p, steps, history_capacity=1024) for p in probs]
+        best = b.tune(2)  # 18 shapes x (1 warm-up + 2) steps
+        say(f"    tuned {best}")
+        assert best["tile_w"] in (64, 128, 256) and best["tile_h"] in (8, 16, 32)
+        assert best["persistent"] in (0, 1) and best["us_per_step"] > 0
+        info = b.info()
+        assert (info["tile_w"], info["tile_h"]) == (best["tile_w"], best["tile_h"])
+        b.run(steps)
+        for s, p in zip(slots, probs):
+            t, rem, u = b.status(s)
+            say(f"    {p.name} side {p.nx} tau {p.tau:.3f}: t={t} unstable={u}")
+            n = steps if u < 0 else u
+            assert (t, rem) == (n, 0)
+            # fields do not depend on the tile shape (the mass history's last
+            # bits do: partials are summed per tile)
+            a_mom, _, a_u = alone(L, p, n, "f64")
+            assert a_u == u and same(b.moments(s), a_mom)
+
+
+def test_unstable_instance_stops_alone(L):
+    """A Zhao-Yong droplet breaks down within a few dozen steps; in a batch
+    it stops at that step and the others are untouched."""
+    bad = cfg.cfg1("zhao_yong", "none")
+    good = small_mix(2)
+    with L.Batch(storage="f64", eos="cs", max_instances=4, tile_w=128, tile_h=16,
+                 arena_bytes=1 << 29) as b:
+        kb = b.add(bad, 100, history_capacity=256)
+        kg = [b.add(p, 100, history_capacity=256) for p in good]
+        b.run(100)
+        t, rem, u = b.status(kb)
+        a = alone(L, bad, 100, "f64", 128, 16)
+        say(f"    zhao-yong unstable at {u} (alone {a[2]}), stopped at t={t}")
+        assert u == a[2] and u > 0 and rem == 0 and t == u
+        for k, p in zip(kg, good):
+            assert b.status(k)[:3] == (100, 0, -1)
+            assert same(b.moments(k), alone(L, p, 100, "f64", 128, 16)[0])
+
+
+def test_fp32_batch_within_gate_of_fp64(L):
+    """Batched workload gate, FP32 storage against the FP64 form after 1000
+    steps (max-norm relative over fluid nodes): rho within 1e-5; u within
+    3e-5.  These droplets carry only spurious currents (|u| of order 1e-3),
+    so the velocity norm sees the FP32 rounding of populations about 1e4
+    times larger than the velocities they encode (up to 1.3e-5 measured)."""
+    from tests._lib import rel_err
+    probs = [p for p in small_mix(8, 64, 256, seed=4)]
+    with L.Batch(storage="f32", eos="cs", max_instances=8, arena_bytes=1 << 30) as b:
+        slots = [b.add(p, 1000, history_capacity=2048) for p in probs]
+        b.run(1000)
+        for s, p in zip(slots, probs):
+            t, rem, u = b.status(s)
+            ref, _, ru = alone(L, p, 1000, "f64")
+            if u >= 0 or ru >= 0:
+                say(f"    {p.name}: unstable (batch {u}, fp64 {ru})")
+                assert (u >= 0) == (ru >= 0)
+                continue
+            fl = ~p.solid.astype(bool)
+            g = b.moments(s)
+            e = [rel_err(g[i], ref[i], fl) for i in range(3)]
+            say(f"    {p.name} side {p.nx} tau {p.tau:.3f}: {e}")
+            assert e[0] <= 1e-5 and max(e[1:]) <= 3e-5
+
+
+def test_full_batch_512_sampled(L):
+    """The 512-instance mix (sides 64..768) in one batch, FP32, in the
+    benchmark's launch shape: sampled instances equal their runs alone."""
+    probs = [cfg.batch_instance(k) for k in range(512)]
+    nodes = sum(p.nx * p.ny for p in probs)
+    say(f"[gpu] 512 instances, {nodes} nodes")
+    with L.Batch(storage="f32", eos="cs", max_instances=512, arena_bytes=24 << 30) as b:
+        slots = [b.add(p, 60, history_capacity=128) for p in probs]
+        b.run(60)
+        info = b.info()
+        say(f"    {info}")
+        unstable = [k for k in range(512) if b.status(slots[k])[2] >= 0]
+        say(f"    unstable instances within 60 steps: {len(unstable)}")
+        for k in (0, 17, 255, 511):
+            t, rem, u = b.status(slots[k])
+            assert rem == 0
+            assert same(b.moments(slots[k]), alone(L, probs[k], 60 if u < 0 else u, "f32")[0])
+
+
+def test_server_result_same_alone_and_in_mix(L):
+    """Requests of mixed sizes and lengths arrive while others run; each
+    result equals the request run alone.  The arena holds only part of the
+    mix at once, so admission waits for memory."""
+    probs = small_mix(8, 64, 200, seed=5)
+    steps = [30 + 17 * k for k in range(8)]
+    with L.Server(chunk_steps=16, storage="f64", eos="cs", max_instances=8,
+                  tile_w=128, tile_h=16, arena_bytes=24 << 20) as srv:
+        ids = {}
+        pending = list(range(8))
+        done = {}
+        rounds = 0
+        while len(done) < 8:
+            rounds += 1
+            assert rounds < 1000
+            if pending and rounds % 2 == 1:  # a new request every other round
+                k = pending.pop(0)
+                ids[srv.submit(probs[k], steps[k], history_capacity=1024)] = k
+            for rid in srv.progress():
+                k = ids[rid]
+                done[k] = srv.result(rid)
+                srv.release(rid)
+            info = srv.info()
+            assert info["arena_used"] <= info["arena_bytes"]
+        say(f"    {rounds} rounds, {srv.info()}")
+        for k in range(8):
+            r = done[k]
+            n = steps[k] if r["unstable_step"] < 0 else r["unstable_step"]
+            a_mom, a_hist, a_u = alone(L, probs[k], n, "f64", 128, 16)
+            assert r["unstable_step"] == a_u and r["steps"] == n
+            assert same((r["rho"], r["ux"], r["uy"]), a_mom)
+            assert r["mass0"] == a_hist[0] and r["mass"] == a_hist[-1]
+
+
+def test_server_rejects_what_never_fits(L):
+    big = cfg.batch_instance(0, side_lo=700, side_hi=768)
+    small = cfg.batch_instance(1, side_lo=64, side_hi=80)
+    with L.Server(chunk_steps=8, storage="f32", eos="cs", max_instances=4,
+                  arena_bytes=8 << 20) as srv:
+        rb = srv.submit(big, 10)
+        rs = srv.submit(small, 10, history_capacity=64)
+        got = []
+        for _ in range(20):
+            got += srv.progress()
+            if rs in got:
+                break
+        info = srv.info()
+        assert rs in got and rb not in got
+        assert info["rejected"] == 1 and info["queued"] == 0
