@@ -110,6 +110,175 @@ def precision_leg(steps, warmup, stream, prof_every):
     return out
 
 
+def rel_err_fields(p, g, ref):
+    """max |g - ref| / max |ref| of rho, ux, uy over fluid nodes."""
+    import numpy as np
+
+    fl = ~p.solid.astype(bool)
+    out = {}
+    for i, nm in enumerate(("rho", "ux", "uy")):
+        den = float(np.max(np.abs(ref[i][fl])))
+        out[f"err_{nm}"] = float(np.max(np.abs(g[i][fl] - ref[i][fl])) / den) if den else None
+    return out
+
+
+def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
+    """The batched mix: n_inst droplet-on-cylinder instances (sides
+    64..768, T/Tc, tau drawn per instance), one batch, autotuned, each
+    instance run `steps` steps.  Sampled instances are checked against the
+    FP64 plain form; a sample run one by one gives the unbatched rate."""
+    import numpy as np
+    import torch
+
+    from lbm_inputs import configs as cfg
+    from paper_1908_09235_amd import lbm
+
+    probs = [cfg.batch_instance(k) for k in range(n_inst)]
+    fluid = np.array([p.fluid_nodes for p in probs], dtype=np.float64)
+    cap = 1 << int(np.ceil(np.log2(steps + 2)))
+    b = lbm.Batch(storage=storage, eos="cs", max_instances=n_inst, arena_bytes=48 << 30)
+    t0 = time.perf_counter()
+    slots = [b.add(p, steps, history_capacity=cap) for p in probs]
+    t_build = time.perf_counter() - t0
+    tuned = b.tune(tune_steps)
+    b.sync()
+    done0 = np.array([b.status(s)[0] for s in slots], dtype=np.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps)
+    b.sync()
+    t1 = time.perf_counter()
+    st = [b.status(s) for s in slots]
+    done = np.array([x[0] for x in st], dtype=np.float64) - done0
+    unstable = sum(1 for x in st if x[2] >= 0)
+    secs = t1 - t0
+    lu = float((fluid * done).sum())
+    out = {"workload": f"droplet_cylinder_mix_{n_inst}", "instances": n_inst,
+           "storage": storage, "arith": ARITH[storage], "steps": steps,
+           "nodes": int(sum(p.nx * p.ny for p in probs)),
+           "fluid_nodes": int(fluid.sum()), "seconds": round(secs, 3),
+           "solves_per_s": round(n_inst / secs, 2),
+           "mlups": round(lu / secs / 1e6, 1), "unstable": unstable,
+           "tuned": tuned, "graph_steps": 32, "build_seconds": round(t_build, 2),
+           "info": b.info()}
+    # sampled per-instance error against the FP64 plain form, same steps
+    errs = []
+    for k in sample:
+        t_k, _, u_k = st[k]
+        n = int(t_k)
+        g = b.moments(slots[k])
+        with lbm.Domain(probs[k], storage="f64") as d:
+            try:
+                d.step(n)
+            except lbm.LbmError:
+                pass
+            ref = d.moments()
+        errs.append({"instance": k, "side": probs[k].nx, "steps": n, "unstable": u_k,
+                     **rel_err_fields(probs[k], g, ref)})
+    out["sample_vs_fp64"] = errs
+    b.close()
+    # the unbatched rate: a sample of instances one after another, one
+    # domain and two launches per step each
+    k_alone = list(range(0, n_inst, max(1, n_inst // 16)))
+    lu_a, t_a = 0.0, 0.0
+    for k in k_alone:
+        with lbm.Domain(probs[k], storage=storage, stream=stream) as d:
+            d.step(5)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            try:
+                d.step(alone_steps)
+            except lbm.LbmError:
+                pass
+            torch.cuda.synchronize()
+            t_a += time.perf_counter() - ta
+            lu_a += fluid[k] * alone_steps
+    out["one_by_one_mlups"] = round(lu_a / t_a / 1e6, 1)
+    out["one_by_one_sample"] = f"{len(k_alone)} instances x {alone_steps} steps"
+    return out
+
+
+def serve_leg(storage, seconds, rates, chunk, pool):
+    """The served workload: Poisson arrivals of droplet-on-cylinder
+    requests (95 % the batched mix, 5 % 2048^2; 2000..20000 steps each) into
+    one server.  First a saturated run (every request present at t = 0)
+    measures the sustainable completion rate, then the arrival rates in
+    `rates` (fractions of it) give time-to-solution percentiles."""
+    import numpy as np
+
+    from lbm_inputs import configs as cfg
+    from paper_1908_09235_amd import lbm
+
+    probs = {k: cfg.batch_instance(k) for k in range(pool)}
+    probs["big"] = cfg.cfg2a()
+    nodes = {k: p.nx * p.ny for k, p in probs.items()}
+    e_nodes = 0.95 * np.mean([nodes[k] for k in range(pool)]) + 0.05 * nodes["big"]
+    e_steps = 11000.0
+
+    def run(reqs, horizon):
+        srv = lbm.Server(chunk_steps=chunk, storage=storage, eos="cs", max_instances=4096,
+                         arena_bytes=96 << 30)
+        arrive, done_t, info = {}, {}, {}
+        i = 0
+        t0 = time.perf_counter()
+        lu = 0.0
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i][0] <= now:
+                _, key, steps = reqs[i]
+                rid = srv.submit(probs[key], steps, history_capacity=1 << 15)
+                arrive[rid] = (reqs[i][0], key, steps)
+                i += 1
+            fin = srv.progress()
+            now = time.perf_counter() - t0
+            for rid in fin:
+                r = srv.result(rid, fields=False)
+                done_t[rid] = now
+                info[rid] = r
+                lu += probs[arrive[rid][1]].fluid_nodes * r["steps"]
+                srv.release(rid)
+            if (i == len(reqs) and len(done_t) == len(reqs)) or now > horizon:
+                break
+            if not fin and srv.info()["running"] == 0 and i < len(reqs):
+                time.sleep(min(0.002, max(0.0, reqs[i][0] - now)))
+        wall = time.perf_counter() - t0
+        st = srv.info()
+        srv.close()
+        lat = np.array([done_t[r] - arrive[r][0] for r in done_t])
+        drift = [abs(info[r]["mass"] - info[r]["mass0"]) / info[r]["mass0"]
+                 for r in info if info[r]["unstable_step"] < 0 and np.isfinite(info[r]["mass0"])]
+        return {"requests": len(reqs), "completed": len(done_t), "wall_s": round(wall, 2),
+                "solves_per_s": round(len(done_t) / wall, 2),
+                "mlups": round(lu / wall / 1e6, 1),
+                "p50_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+                "p99_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+                "unstable": sum(1 for r in info.values() if r["unstable_step"] >= 0),
+                "max_mass_drift": float(max(drift)) if drift else None,
+                "chunks": st["chunks"], "unfinished": len(reqs) - len(done_t)}
+
+    # saturated: enough requests for about `seconds` of work at the
+    # batched rate, all present at once
+    sat_reqs = [(0.0, k, s) for (_, k, s) in cfg.request_stream(1000.0, 0.12, pool=pool)]
+    sat = run(sat_reqs, 10 * seconds)
+    lam_max = sat["solves_per_s"]
+    sweep = []
+    for f in rates:
+        lam = max(lam_max * f, 0.1)
+        reqs = cfg.request_stream(lam, seconds, pool=pool)
+        r = run(reqs, 3 * seconds)
+        r["rate"] = round(lam, 2)
+        r["rate_fraction"] = f
+        sweep.append(r)
+    offered = 200.0 * e_nodes * e_steps
+    return {"workload": "droplet_cylinder_requests", "storage": storage,
+            "chunk_steps": chunk, "pool": pool,
+            "mean_nodes_per_request": round(float(e_nodes)),
+            "mean_steps_per_request": e_steps,
+            "offered_lups_at_200_per_s": offered,
+            "offered_vs_fp32_hbm_roofline": round(offered / (PEAK_HBM_GBS * 1e9 / 72.0), 2),
+            "saturated": sat, "sustainable_rate_per_s": lam_max, "sweep": sweep}
+
+
 def cpu_baseline(p, seconds):
     from oracle import core as ora
 
@@ -141,6 +310,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precision-steps", type=int, default=2000,
                     help="steps of the 8192 x 4096 precision-form comparison (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=5000,
+                    help="steps of each instance of the batched mix (0: skip)")
+    ap.add_argument("--batch-instances", type=int, default=512)
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="arrival window of each served run (0: skip)")
+    ap.add_argument("--serve-chunk", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter "
                          "calibration under rocprofv3)")
@@ -197,6 +372,14 @@ def main():
     if a.precision_steps > 0:
         prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_every)
 
+    batch = None
+    if a.batch_steps > 0:
+        batch = batch_leg(a.batch_steps, a.batch_instances, "f32", stream, 3,
+                          [0, 101, 257, a.batch_instances - 1], 500)
+    serve = None
+    if a.serve_seconds > 0:
+        serve = serve_leg("f32", a.serve_seconds, [0.5, 0.8, 1.0], a.serve_chunk, 128)
+
     cpu = None
     if a.cpu_seconds > 0:
         n, t = cpu_baseline(p, a.cpu_seconds)
@@ -228,6 +411,8 @@ def main():
         "cpu_baseline": cpu,
         "also": also,
         "precision": prec,
+        "batched": batch,
+        "served": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -279,3 +279,21 @@ def batch_instance(k: int, seed: int = 4, side_lo=64, side_hi=768,
                  rule=rule, fix=fix, name=f"inst{k}")
     p.meta.update(side=side, rc=rc, rd=rd, t_over_tc=t)
     return p
+
+
+def request_stream(rate: float, duration: float, pool: int = 128, seed: int = 5,
+                   big_fraction: float = 0.05, steps_lo: int = 2000,
+                   steps_hi: int = 20000):
+    """Arrivals of the served workload over [0, duration): Poisson at
+    `rate` per second (exponential gaps); each request is instance
+    k ~ U{0..pool-1} of the batched mix or, with probability big_fraction,
+    the 2048^2 droplet ("big"), and runs steps ~ U{steps_lo..steps_hi}.
+    Returns [(arrival_s, key, steps)]."""
+    rs = Stream(seed, 1)
+    out, t = [], 0.0
+    while True:
+        t += -math.log(1.0 - rs.uniform()) / rate
+        if t >= duration:
+            return out
+        key = "big" if rs.uniform() < big_fraction else rs.integers(0, pool - 1)
+        out.append((t, key, rs.integers(steps_lo, steps_hi)))
