@@ -567,7 +567,8 @@ int lbm_batch_info(lbm_batch* b, int64_t out[8]) {
     for (lbm_domain* d : b->inst) {
         if (!d) continue;
         ++n;
-        tiles += ((d->nx + b->tile_w - 1) / b->tile_w) * (long long)((d->ny + b->tile_h - 1) / b->tile_h);
+        const int sc = strip_cols(b->tile_w);
+        tiles += ((d->nx + sc - 1) / sc) * (long long)((d->ny + b->tile_h - 1) / b->tile_h);
         lblk += (d->nslot_links + 255) / 256;
     }
     out[0] = n;

@@ -104,24 +104,27 @@ __device__ __forceinline__ R dens(const R f[9]) {
 }
 
 // One row of a strip in flight, in the storage type: the pulled populations
-// of the thread's column and, in wave 0, of a halo column, with their flags
-// and (solid nodes) the wall psi.
+// of the thread's column with its flags and (solid nodes) the wall psi.
 template <typename S, typename R>
 struct RowLoad {
     S f[9];
-    S h[9];
-    R pw, hpw;
-    uint8_t fl, hfl;
+    R pw;
+    uint8_t fl;
 };
 
-// One tile of the main pass: strip `strip` of tile_w = blockDim.x columns,
-// rows of segment `seg`.  Writes the tile's mass partial to partial[tile].
+// Columns a strip updates: a workgroup of tile_w lanes also pulls the
+// column on either side of its strip, for psi only.
+__host__ __device__ constexpr int strip_cols(int tile_w) { return tile_w - 2; }
+
+// One tile of the main pass: strip `strip` (at most strip_cols(blockDim.x)
+// columns, plus one psi-only column on each side), rows of segment `seg`.
+// Writes the tile's mass partial to partial[tile].
 // MOMENTS: write rho, u at every node instead of colliding and storing.
 // DEV: populations are stored as deviations g = f - w rho_ref.
 template <typename S, typename R, int EOS, bool MOMENTS, bool DEV>
 __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& ph,
                                           int tile) {
-    __shared__ R ring[4][kMaxTileW + 2];
+    __shared__ R ring[4][kMaxTileW];
     __shared__ double wsum[kMaxTileW / 64];
     constexpr unsigned ES = sizeof(S), RS = sizeof(R);
     const unsigned pitch = (unsigned)a.pitch;
@@ -136,20 +139,19 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     const int tid = threadIdx.x;
     const int W = blockDim.x;
     const int seg = tile / a.nstrips, strip = tile - seg * a.nstrips;
-    const int x0 = strip * W;
-    const int ncols = min(W, a.nx - x0);
-    const bool act = tid < ncols;
-    const unsigned x = act ? x0 + tid : x0;
+    // the nstrips = ceil(nx / strip_cols) strips share the columns evenly
+    const int x0 = (int)(((unsigned long long)strip * (unsigned)a.nx) / (unsigned)a.nstrips);
+    const int ncols =
+        (int)(((unsigned long long)(strip + 1) * (unsigned)a.nx) / (unsigned)a.nstrips) - x0;
+    // lane t pulls column x0 - 1 + t; lanes 1..ncols update theirs, lanes 0
+    // and ncols + 1 only supply psi, the rest are idle
+    const bool act = tid <= ncols + 1;
+    const bool upd = tid >= 1 && tid <= ncols;
+    int xi = x0 - 1 + (act ? tid : 1);
+    xi = xi < 0 ? xi + a.nx : (xi >= a.nx ? xi - a.nx : xi);
+    const unsigned x = (unsigned)xi;
     const unsigned xm = x == 0 ? a.nx - 1 : x - 1;
     const unsigned xp = x == (unsigned)a.nx - 1 ? 0 : x + 1;
-    // wave 0 also pulls the two halo columns (even lanes left, odd right)
-    const bool hw = tid < 64;
-    const unsigned hxl = x0 == 0 ? a.nx - 1 : x0 - 1;
-    const unsigned hxr = x0 + ncols == a.nx ? 0 : x0 + ncols;
-    const unsigned hx = (tid & 1) ? hxr : hxl;
-    const unsigned hxm = hx == 0 ? a.nx - 1 : hx - 1;
-    const unsigned hxp = hx == (unsigned)a.nx - 1 ? 0 : hx + 1;
-    const int hcol = (tid & 1) ? ncols + 1 : 0;
     // rows: even segments march up, odd ones down, so that neighbouring
     // segments reach their shared boundary rows at the same time
     const int y0 = seg * a.tile_h;
@@ -162,11 +164,10 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     };
 
     // flags of the next row to issue are loaded one issue ahead
-    uint8_t nfl, nhfl = 0;
+    uint8_t nfl;
     auto load_flags = [&](int k) {
         const unsigned r = (unsigned)row_of(k) * pitch;
         nfl = bload<uint8_t>(rfl, x, r);
-        if (hw) nhfl = bload<uint8_t>(rfl, hx, r);
     };
     auto pull = [&](S f[9], R& pw, uint8_t fl, unsigned c, unsigned cm, unsigned cp,
                     unsigned rm, unsigned r0, unsigned rp, unsigned prow) {
@@ -186,15 +187,13 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     };
     auto issue = [&](int k, RowLoad<S, R>& L) {
         const int y = row_of(k);
-        L.fl = nfl;
-        L.hfl = nhfl;
+        L.fl = act ? nfl : uint8_t(FL_SOLID);  // idle lanes load nothing
         load_flags(k + 1);
         const unsigned r0 = (unsigned)y * pitch * ES;
         const unsigned rm = (unsigned)(y == 0 ? a.ny - 1 : y - 1) * pitch * ES;
         const unsigned rp = (unsigned)(y == a.ny - 1 ? 0 : y + 1) * pitch * ES;
         const unsigned prow = (unsigned)y * pitch * RS;
-        pull(L.f, L.pw, L.fl, x, xm, xp, rm, r0, rp, prow);
-        if (hw) pull(L.h, L.hpw, L.hfl, hx, hxm, hxp, rm, r0, rp, prow);
+        if (act) pull(L.f, L.pw, L.fl, x, xm, xp, rm, r0, rp, prow);
     };
     auto psi_node = [&](const S fs[9], R pw, uint8_t fl) {
         R f[9];
@@ -204,11 +203,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         return (fl & FL_SOLID) ? pw : psi_of<EOS, R>(rho, ph);
     };
     auto publish = [&](const RowLoad<S, R>& L, int slot) {
-        if (act) ring[slot][tid + 1] = psi_node(L.f, L.pw, L.fl);
-        if (hw) {
-            const R hp = psi_node(L.h, L.hpw, L.hfl);
-            if (tid < 2) ring[slot][hcol] = hp;
-        }
+        if (act) ring[slot][tid] = psi_node(L.f, L.pw, L.fl);
     };
 
     double msum = 0.0;
@@ -219,11 +214,11 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         const int sym = dir > 0 ? sm : sp, syp = dir > 0 ? sp : sm;
         publish(Ln, sp);
         __syncthreads();
-        if (act && !(Lc.fl & FL_SOLID)) {
+        if (upd && !(Lc.fl & FL_SOLID)) {
             R fc[9];  // stored form: f, or deviations g
 #pragma unroll
             for (int q = 0; q < 9; ++q) fc[q] = R(Lc.f[q]);
-            const int c = tid + 1;
+            const int c = tid;
             const R drho = dens<R>(fc);
             const R rho = DEV ? ph.rref + drho : drho;
             const R irho = rcp(rho);
@@ -279,7 +274,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
 #pragma unroll
                 for (int q = 0; q < 9; ++q) bstore(S(fc[q] + dh[q]), rd, x * ES, q * pb + r0);
             }
-        } else if (MOMENTS && act) {
+        } else if (MOMENTS && upd) {
             const long long o = (long long)y * a.nx + x;
             const long long n2 = (long long)a.nx * a.ny;
             a.mom_out[o] = 0.0;
@@ -329,8 +324,18 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
                                                 long long* __restrict__ unstable) {
     __shared__ double red[256];
     const int tid = threadIdx.x;
+    // each thread adds partials tid, tid + 256, ... in that order; eight
+    // loads are issued before their additions
     double v = 0.0;
-    for (int i = tid; i < np; i += 256) v += partial[i];
+    int i = tid;
+    for (; i + 7 * 256 < np; i += 8 * 256) {
+        double q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = partial[i + j * 256];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v += q[j];
+    }
+    for (; i < np; i += 256) v += partial[i];
     red[tid] = v;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {

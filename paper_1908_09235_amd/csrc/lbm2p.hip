@@ -71,6 +71,22 @@ void free_domain(lbm_domain* d) {
 
 inline int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
+// The workgroup width with the largest share of lanes that update a node
+// (the wider one within 1 %).
+int default_tile_w(int nx) {
+    int best = 64;
+    double be = 0.0;
+    for (int w : {256, 128, 64}) {
+        const int ns = (nx + strip_cols(w) - 1) / strip_cols(w);
+        const double eff = (double)nx / ((double)ns * w);
+        if (eff > be + 0.01) {
+            be = eff;
+            best = w;
+        }
+    }
+    return best;
+}
+
 inline long long storage_bytes(int storage) {
     return storage == LBM_STORE_F64 ? 8 : storage == LBM_STORE_F16DEV ? 2 : 4;
 }
@@ -358,9 +374,9 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->coll = s->collision;
     d->rule = s->rule;
     d->fix = s->fix;
-    d->tile_w = s->tile_w ? s->tile_w : (nx >= 256 ? 256 : (nx > 64 ? 128 : 64));
-    d->tile_h = s->tile_h ? s->tile_h : 16;
-    d->nstrips = (nx + d->tile_w - 1) / d->tile_w;
+    d->tile_w = s->tile_w ? s->tile_w : default_tile_w(nx);
+    d->tile_h = s->tile_h ? s->tile_h : 8;
+    d->nstrips = (nx + strip_cols(d->tile_w) - 1) / strip_cols(d->tile_w);
     d->nsegs = (ny + d->tile_h - 1) / d->tile_h;
     d->nblocks = d->nstrips * d->nsegs;
     d->cap = s->history_capacity > 0 ? s->history_capacity : (1LL << 20);
@@ -516,7 +532,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
                         (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8)))
         return rc;
     // partials for any tile shape down to 64 x 8 (the batched form retunes)
-    d->partial_cap = std::max(d->nblocks, ((nx + 63) / 64) * ((ny + 7) / 8));
+    d->partial_cap = std::max(d->nblocks, ((nx + strip_cols(64) - 1) / strip_cols(64)) * ((ny + 7) / 8));
     if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->partial_cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
@@ -589,7 +605,8 @@ void domain_free(lbm_domain* d) { free_domain(d); }
 int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h) {
     if (tile_w != 64 && tile_w != 128 && tile_w != 256) return LBM_EINVAL;
     if (tile_h < 1) return LBM_EINVAL;
-    const int ns = (d->nx + tile_w - 1) / tile_w, ng = (d->ny + tile_h - 1) / tile_h;
+    const int sc = strip_cols(tile_w);
+    const int ns = (d->nx + sc - 1) / sc, ng = (d->ny + tile_h - 1) / tile_h;
     if ((long long)ns * ng > d->partial_cap) return LBM_EINVAL;
     d->tile_w = tile_w;
     d->tile_h = tile_h;
