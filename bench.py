@@ -23,8 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-BYTES_PER_POP = {"f64": 8, "f32": 4, "f32_arith32": 4, "f32dev": 4, "f16dev": 2}
-ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32", "f32dev": "f32", "f16dev": "f32"}
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f32_arith32": 4, "f32dev": 4, "f16dev": 2, "f16node": 2}
+# algorithmic bytes per lattice update beyond the 18 populations (the
+# per-node reference read of the FP16 per-node form)
+EXTRA_BYTES = {"f16node": 4}
+ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32", "f32dev": "f32", "f16dev": "f32",
+         "f16node": "f32"}
 
 
 def source_hash():
@@ -89,14 +93,14 @@ def precision_leg(steps, warmup, stream, prof_every):
     fl = ~p.solid.astype(bool)
     out = {"workload": f"{p.name}_bgk_mls_B", "steps": steps}
     ref = None
-    for st in ("f64", "f32", "f32dev", "f16dev"):
+    for st in ("f64", "f32", "f32dev", "f16dev", "f16node"):
         r = run_gpu(p, st, steps, warmup, stream, 0, 0, prof_every, moments=True)
         fluid = r["info"]["fluid_nodes"]
         rec = {"arith": ARITH[st],
                "mlups": round(fluid * steps / r["seconds"] / 1e6, 1),
                "main_kernel_ms": round(r["main_ms"], 5),
-               "main_kernel_gbs": (round(18 * BYTES_PER_POP[st] * fluid /
-                                         (r["main_ms"] * 1e-3) / 1e9, 1)
+               "main_kernel_gbs": (round((18 * BYTES_PER_POP[st] + EXTRA_BYTES.get(st, 0)) *
+                                         fluid / (r["main_ms"] * 1e-3) / 1e9, 1)
                                    if r["main_ms"] > 0 else None),
                "mass_drift": r["drift"]}
         if st == "f64":

@@ -193,6 +193,7 @@ BInst make_inst(lbm_domain* d) {
     I.lc = d->lc;
     I.luw = d->luw;
     I.rref = d->ph64.rref;
+    I.lref = d->lref;
     I.hist = d->hist;
     I.cap = d->cap;
     I.unstable = d->unstable;
@@ -395,7 +396,7 @@ extern "C" {
 
 int lbm_batch_create(const lbm_batch_desc* bd, lbm_batch** out) {
     if (!bd || !out) return LBM_EINVAL;
-    if (bd->storage < LBM_STORE_F64 || bd->storage > LBM_STORE_F16DEV) return LBM_EINVAL;
+    if (bd->storage < LBM_STORE_F64 || bd->storage > LBM_STORE_F16NODE) return LBM_EINVAL;
     if (bd->eos < LBM_EOS_NONE || bd->eos > LBM_EOS_CS) return LBM_EINVAL;
     if (bd->max_instances < 1 || bd->max_instances > (1 << 20)) return LBM_EINVAL;
     if (bd->tile_w != 0 && bd->tile_w != 64 && bd->tile_w != 128 && bd->tile_w != 256)

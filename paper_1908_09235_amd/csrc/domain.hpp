@@ -42,6 +42,8 @@ struct lbm_domain {
     int storage = 0, eos = 0, coll = 0, rule = 0, fix = 0;
     int tile_w = 0, tile_h = 0, nstrips = 0, nsegs = 0, nblocks = 0;
     size_t esize = 8;
+    size_t fbytes = 0;  // one state buffer: nine planes (+ the FP16 per-node
+                        // form's FP32 density plane)
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     uint8_t* flags = nullptr;
@@ -55,6 +57,7 @@ struct lbm_domain {
     double* hist = nullptr;
     long long* unstable = nullptr;
     double* mom_out = nullptr;
+    int* lref = nullptr;   // per link: side slot whose density encodes its ghost
     int nb = 0, nl = 0;
     int nslot_links = 0;
     int *lnode = nullptr, *lmeta = nullptr, *lghost = nullptr, *lxf = nullptr,

@@ -105,11 +105,12 @@ __device__ __forceinline__ R dens(const R f[9]) {
 
 // One row of a strip in flight, in the storage type: the pulled populations
 // of the thread's column with its flags and (solid nodes) the wall psi.
-template <typename S, typename R>
+template <typename S, typename R, int NR>
 struct RowLoad {
     S f[9];
     R pw;
     uint8_t fl;
+    float rr[NR];  // per-node references of the nine source nodes (DEV 2)
 };
 
 // Columns a strip updates: a workgroup of tile_w lanes also pulls the
@@ -120,21 +121,28 @@ __host__ __device__ constexpr int strip_cols(int tile_w) { return tile_w - 2; }
 // columns, plus one psi-only column on each side), rows of segment `seg`.
 // Writes the tile's mass partial to partial[tile].
 // MOMENTS: write rho, u at every node instead of colliding and storing.
-// DEV: populations are stored as deviations g = f - w rho_ref.
-template <typename S, typename R, int EOS, bool MOMENTS, bool DEV>
+// DEV: 0 populations stored as they are; 1 as deviations g = f - w rho_ref
+// from one reference density; 2 as deviations g = f - w r(x) from the
+// density r(x) of the node x whose slot holds g, kept in an FP32 plane
+// after the nine population planes of each buffer.
+template <typename S, typename R, int EOS, bool MOMENTS, int DEV>
 __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& ph,
                                           int tile) {
     __shared__ R ring[4][kMaxTileW];
     __shared__ double wsum[kMaxTileW / 64];
     constexpr unsigned ES = sizeof(S), RS = sizeof(R);
+    constexpr int NR = DEV == 2 ? 9 : 1;
     const unsigned pitch = (unsigned)a.pitch;
     // one resource per buffer; plane and row offsets go in the scalar
     // offset (the whole buffer is below 4 GiB)
     const unsigned pb = (unsigned)(a.plane * ES);
-    const rsrc_t rs = make_rsrc(a.src, 9u * pb);
-    const rsrc_t rd = make_rsrc(a.dst, 9u * pb);
+    const unsigned bbytes = 9u * pb + (DEV == 2 ? (unsigned)a.plane * 4u : 0u);
+    const rsrc_t rs = make_rsrc(a.src, bbytes);
+    const rsrc_t rd = make_rsrc(a.dst, bbytes);
     const rsrc_t rfl = make_rsrc(a.flags, pitch * (unsigned)a.ny);
     const rsrc_t rpw = make_rsrc(a.psiw, pitch * (unsigned)a.ny * RS);
+    // DEV 2: the FP32 density plane follows the nine population planes
+    const unsigned rbase = 9u * pb;
 
     const int tid = threadIdx.x;
     const int W = blockDim.x;
@@ -169,11 +177,25 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         const unsigned r = (unsigned)row_of(k) * pitch;
         nfl = bload<uint8_t>(rfl, x, r);
     };
-    auto pull = [&](S f[9], R& pw, uint8_t fl, unsigned c, unsigned cm, unsigned cp,
-                    unsigned rm, unsigned r0, unsigned rp, unsigned prow) {
+    auto pull = [&](S f[9], R& pw, float rr[NR], uint8_t fl, unsigned c, unsigned cm,
+                    unsigned cp, unsigned rm, unsigned r0, unsigned rp, unsigned prow) {
         if (fl & FL_SOLID) {
             pw = bload<R>(rpw, c * RS, prow);
         } else {
+            if constexpr (DEV == 2) {
+                // the source nodes' densities, rows of the FP32 plane
+                const unsigned qm = rbase + rm / ES * 4u, q0 = rbase + r0 / ES * 4u,
+                               qp = rbase + rp / ES * 4u;
+                rr[0] = bload<float>(rs, c * 4u, q0);
+                rr[1 % NR] = bload<float>(rs, cm * 4u, q0);
+                rr[2 % NR] = bload<float>(rs, c * 4u, qm);
+                rr[3 % NR] = bload<float>(rs, cp * 4u, q0);
+                rr[4 % NR] = bload<float>(rs, c * 4u, qp);
+                rr[5 % NR] = bload<float>(rs, cm * 4u, qm);
+                rr[6 % NR] = bload<float>(rs, cp * 4u, qm);
+                rr[7 % NR] = bload<float>(rs, cp * 4u, qp);
+                rr[8 % NR] = bload<float>(rs, cm * 4u, qp);
+            }
             f[0] = bload<S>(rs, c * ES, r0);
             f[1] = bload<S>(rs, cm * ES, 1 * pb + r0);
             f[2] = bload<S>(rs, c * ES, 2 * pb + rm);
@@ -185,7 +207,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             f[8] = bload<S>(rs, cm * ES, 8 * pb + rp);
         }
     };
-    auto issue = [&](int k, RowLoad<S, R>& L) {
+    auto issue = [&](int k, RowLoad<S, R, NR>& L) {
         const int y = row_of(k);
         L.fl = act ? nfl : uint8_t(FL_SOLID);  // idle lanes load nothing
         load_flags(k + 1);
@@ -193,34 +215,38 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         const unsigned rm = (unsigned)(y == 0 ? a.ny - 1 : y - 1) * pitch * ES;
         const unsigned rp = (unsigned)(y == a.ny - 1 ? 0 : y + 1) * pitch * ES;
         const unsigned prow = (unsigned)y * pitch * RS;
-        if (act) pull(L.f, L.pw, L.fl, x, xm, xp, rm, r0, rp, prow);
+        if (act) pull(L.f, L.pw, L.rr, L.fl, x, xm, xp, rm, r0, rp, prow);
     };
-    auto psi_node = [&](const S fs[9], R pw, uint8_t fl) {
-        R f[9];
+    // stored form -> populations (DEV 2) or the stored form itself
+    auto decode = [&](const RowLoad<S, R, NR>& L, R f[9]) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = R(fs[q]);
-        const R rho = DEV ? ph.rref + dens<R>(f) : dens<R>(f);
-        return (fl & FL_SOLID) ? pw : psi_of<EOS, R>(rho, ph);
+        for (int q = 0; q < 9; ++q)
+            f[q] = DEV == 2 ? R(L.f[q]) + R(wt(q)) * R(L.rr[q % NR]) : R(L.f[q]);
     };
-    auto publish = [&](const RowLoad<S, R>& L, int slot) {
-        if (act) ring[slot][tid] = psi_node(L.f, L.pw, L.fl);
+    auto psi_node = [&](const RowLoad<S, R, NR>& L) {
+        R f[9];
+        decode(L, f);
+        const R rho = DEV == 1 ? ph.rref + dens<R>(f) : dens<R>(f);
+        return (L.fl & FL_SOLID) ? L.pw : psi_of<EOS, R>(rho, ph);
+    };
+    auto publish = [&](const RowLoad<S, R, NR>& L, int slot) {
+        if (act) ring[slot][tid] = psi_node(L);
     };
 
     double msum = 0.0;
     // row k: collide with psi of rows k-1, k, k+1; then prefetch row k+3
-    auto step = [&](int k, RowLoad<S, R>& Lc, RowLoad<S, R>& Ln, RowLoad<S, R>& Lf) {
+    auto step = [&](int k, RowLoad<S, R, NR>& Lc, RowLoad<S, R, NR>& Ln, RowLoad<S, R, NR>& Lf) {
         const int y = row_of(k);
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
         const int sym = dir > 0 ? sm : sp, syp = dir > 0 ? sp : sm;
         publish(Ln, sp);
         __syncthreads();
         if (upd && !(Lc.fl & FL_SOLID)) {
-            R fc[9];  // stored form: f, or deviations g
-#pragma unroll
-            for (int q = 0; q < 9; ++q) fc[q] = R(Lc.f[q]);
+            R fc[9];  // f, or (DEV 1) the deviations g
+            decode(Lc, fc);
             const int c = tid;
             const R drho = dens<R>(fc);
-            const R rho = DEV ? ph.rref + drho : drho;
+            const R rho = DEV == 1 ? ph.rref + drho : drho;
             const R irho = rcp(rho);
             R Fx = R(0), Fy = R(0);
             if constexpr (EOS != EOS_NONE) {
@@ -247,12 +273,18 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             if constexpr (MOMENTS) {
                 const long long o = (long long)y * a.nx + x;
                 const long long n2 = (long long)a.nx * a.ny;
-                a.mom_out[o] = DEV ? double(ph.rref) + double(drho) : double(rho);
+                a.mom_out[o] = DEV == 1 ? double(ph.rref) + double(drho) : double(rho);
                 a.mom_out[n2 + o] = double(ux);
                 a.mom_out[2 * n2 + o] = double(uy);
             } else {
                 // FP64 density (the deviation forms add the reference here)
-                const double rho_d = DEV ? double(ph.rref) + double(drho) : double(rho);
+                double rho_d = DEV == 1 ? double(ph.rref) + double(drho) : double(rho);
+                if constexpr (DEV == 2) {
+                    rho_d = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        rho_d += double(Lc.f[q]) + wt(q) * double(Lc.rr[q % NR]);
+                }
                 msum += rho_d;
                 if (Lc.fl & (FL_SAVE_MOM | FL_SAVE_F)) {
                     const int slot = a.side_idx[(unsigned)y * pitch + x];
@@ -264,15 +296,23 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
                     if (Lc.fl & FL_SAVE_F) {
 #pragma unroll
                         for (int q = 0; q < 9; ++q)
-                            a.side_f[9 * slot + q] =
-                                DEV ? double(fc[q]) + wt(q) * double(ph.rref) : double(fc[q]);
+                            a.side_f[9 * slot + q] = DEV == 1
+                                                             ? double(fc[q]) + wt(q) * double(ph.rref)
+                                                             : double(fc[q]);
                     }
                 }
                 R dh[9];
                 collide<R>(fc, rho, drho, ux, uy, Fx, Fy, ph, dh);
                 const unsigned r0 = (unsigned)y * pitch * ES;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) bstore(S(fc[q] + dh[q]), rd, x * ES, q * pb + r0);
+                for (int q = 0; q < 9; ++q) {
+                    // DEV 2: re-encoded against this node's density,
+                    // g* = g + w (r(x - e) - rho) + dh, without forming f
+                    const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(Lc.rr[q % NR]) - rho)) + dh[q]
+                                         : fc[q] + dh[q];
+                    bstore(S(v), rd, x * ES, q * pb + r0);
+                }
+                if constexpr (DEV == 2) bstore(float(rho), rd, x * 4u, rbase + (unsigned)y * pitch * 4u);
             }
         } else if (MOMENTS && upd) {
             const long long o = (long long)y * a.nx + x;
@@ -284,7 +324,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         if (k + 3 <= H) issue(k + 3, Lc);  // Lc is free again
     };
 
-    RowLoad<S, R> A, B, C;
+    RowLoad<S, R, NR> A, B, C;
     load_flags(-1);
     issue(-1, C);
     publish(C, 0);
@@ -312,7 +352,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     }
 }
 
-template <typename S, typename R, int EOS, bool MOMENTS, bool DEV>
+template <typename S, typename R, int EOS, bool MOMENTS, int DEV>
 __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
     main_tile<S, R, EOS, MOMENTS, DEV>(a, ph, xcd_tile(blockIdx.x, gridDim.x));
 }
@@ -377,6 +417,7 @@ struct BndArgs {
     int nslot;                       // link slots, padding included
     const int* __restrict__ lnode;   // x_b (pitch layout)
     const int* __restrict__ lmeta;   // dir | kind << 4 | len << 8 | pos << 12
+                                     // | (DEV 2: sets the ghost's density) << 16
     const int* __restrict__ lghost;  // solid neighbour x_s
     const int* __restrict__ lxf;     // x_f (or -1)
     const int* __restrict__ lxff;    // x_ff (or -1)
@@ -388,6 +429,8 @@ struct BndArgs {
     const double* __restrict__ side_f;
     long long plane;
     double rref;                     // deviation storage reference (else 0)
+    const int* __restrict__ lref;    // DEV 2: side slot whose density encodes
+                                     // the ghost (one boundary node per ghost)
     int fix;                         // 0 none, 1 A, 2 B, 3 Bao
     // reduction of the previous main launch's mass partials (last block)
     const double* __restrict__ partial;
@@ -401,7 +444,7 @@ struct BndArgs {
 constexpr int LK_PAD = 15;
 
 // Block `blk` of 256 link slots.
-template <typename S, bool DEV>
+template <typename S, int DEV>
 __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs& b,
                                                int blk) {
     __shared__ double s_fab[256], s_inc[256], s_chi[256], s_br[256], s_wall[256];
@@ -414,8 +457,11 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
     const bool active = kind != LK_PAD;
     const long long P = b.plane;
     // stored form -> population
+    // DEV 2: densities of the nodes, after the nine population planes
+    float* const rpl = reinterpret_cast<float*>(A + 9 * P);
     auto ld = [&](int q, int n) {
-        return DEV ? double(A[q * P + n]) + wt(q) * b.rref : double(A[q * P + n]);
+        if constexpr (DEV == 2) return double(A[q * P + n]) + wt(q) * double(rpl[n]);
+        return DEV == 1 ? double(A[q * P + n]) + wt(q) * b.rref : double(A[q * P + n]);
     };
     int node = 0;
     double fab = 0.0, r = 0.0, ch = 0.0, bk = 0.0, wl = 0.0;
@@ -499,7 +545,18 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
         }
         __syncthreads();
     }
-    if (active) A[opp(d) * P + b.lghost[i]] = S(DEV ? r - wt(d) * b.rref : r);
+    if (active) {
+        const int g = b.lghost[i];
+        double enc = DEV == 1 ? wt(d) * b.rref : 0.0;
+        if constexpr (DEV == 2) {
+            // every link into ghost g encodes against the same density: that
+            // of one boundary node next to it, which one of them records
+            const float rg = float(b.side_mom[3 * b.lref[i]]);
+            if ((meta >> 16) & 1) rpl[g] = rg;
+            enc = wt(d) * double(rg);
+        }
+        A[opp(d) * P + g] = S(r - enc);
+    }
     if (head && b.fix == 1) {
         // Eq. (15) without the wall momentum, added to the rest population
         // (Eq. 18)
@@ -513,7 +570,7 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
 }
 
 // The last block reduces the previous main pass's mass partials.
-template <typename S, bool DEV>
+template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
     if (blockIdx.x == gridDim.x - 1) {
         if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
@@ -529,7 +586,8 @@ __global__ void k_init_scatter(S* __restrict__ B, const uint8_t* __restrict__ fl
                                const double* __restrict__ rho0,
                                const double* __restrict__ ux0,
                                const double* __restrict__ uy0, int nx, int ny,
-                               int pitch, long long plane, double rref) {
+                               int pitch, long long plane, double rref,
+                               const float* __restrict__ ref) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= nx || y >= ny) return;
@@ -544,7 +602,8 @@ __global__ void k_init_scatter(S* __restrict__ B, const uint8_t* __restrict__ fl
         int xs = x - cx(a), ys = y - cy(a);
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
         ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-        B[a * plane + ys * pitch + xs] = S(f - wt(a) * rref);
+        const double r0 = ref ? double(ref[ys * pitch + xs]) : rref;
+        B[a * plane + ys * pitch + xs] = S(f - wt(a) * r0);
     }
 }
 
@@ -585,6 +644,7 @@ struct BInst {
     const int *lnode, *lmeta, *lghost, *lxf, *lxff, *lslotb, *lslotf;
     const double *lc, *luw;
     double rref;
+    const int* lref;
     double* hist;
     long long cap;
     long long* unstable;
@@ -633,7 +693,7 @@ __device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long 
     return a;
 }
 
-template <typename S, typename R, int EOS, bool DEV>
+template <typename S, typename R, int EOS, int DEV>
 __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
     g = __builtin_amdgcn_readfirstlane(g);
     const int2 te = b.tiles[g];
@@ -649,7 +709,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
 // the other queues in turn, until all are empty.  The queues hold
 // contiguous runs of the tile list, so one XCD works through compact
 // pieces of the same instances and finds their halos in its L2.
-template <typename S, typename R, int EOS, bool DEV>
+template <typename S, typename R, int EOS, int DEV>
 __global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
     if (!b.persistent) {
         batch_tile<S, R, EOS, DEV>(b, xcd_tile(blockIdx.x, gridDim.x));
@@ -680,7 +740,7 @@ __global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
     }
 }
 
-template <typename S, bool DEV>
+template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
     const int n = *b.nlblk;
     for (int k = blockIdx.x; k < n; k += gridDim.x) {
@@ -703,6 +763,7 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.side_f = I.side_f;
         a.plane = I.plane;
         a.rref = I.rref;
+        a.lref = I.lref;
         a.fix = I.fix;
         a.partial = nullptr;
         a.np = 0;

@@ -22,6 +22,7 @@ struct Ctx {
     double* side_f;
     double* partial;
     double* mom_out;
+    const float* ref;  // init: density plane of the buffer being filled (or null)
     Phys<double> ph;  // converted to the compute type by the launcher
     hipStream_t stream;
 };

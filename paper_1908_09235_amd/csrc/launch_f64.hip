@@ -20,12 +20,12 @@ void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
                        hist, slot, t, unstable);
 }
 
-void launch_batch_f64(const BatchLaunch& L) { batch_any<double, double, false>(L); }
+void launch_batch_f64(const BatchLaunch& L) { batch_any<double, double, 0>(L); }
 void launch_batch_reduce(const BatchLaunch& L) {
     hipLaunchKernelGGL(k_reduce_batch<0>, dim3(L.red_grid), dim3(256), 0, L.stream, L.args);
 }
 int batch_occupancy_f64(int eos, int, int tile_w) {
-    return occupancy_any<double, double, false>(eos, tile_w);
+    return occupancy_any<double, double, 0>(eos, tile_w);
 }
 
 }  // namespace lbm

@@ -10,7 +10,7 @@ Phys<R> convert(const Phys<double>& d) {
     return phys_as<R>(d);
 }
 
-template <typename S, typename R, int EOS, bool MOM, bool DEV>
+template <typename S, typename R, int EOS, bool MOM, int DEV>
 void main_t(const Ctx& c, const S* src, S* dst) {
     MainArgs<S> a{};
     a.src = src;
@@ -33,7 +33,7 @@ void main_t(const Ctx& c, const S* src, S* dst) {
                        c.stream, a, convert<R>(c.ph));
 }
 
-template <typename S, typename R, bool MOM, bool DEV>
+template <typename S, typename R, bool MOM, int DEV>
 void main_s(const Ctx& c, const void* src, void* dst) {
     const S* s = static_cast<const S*>(src);
     S* t = static_cast<S*>(dst);
@@ -42,13 +42,13 @@ void main_s(const Ctx& c, const void* src, void* dst) {
     else main_t<S, R, EOS_CS, MOM, DEV>(c, s, t);
 }
 
-template <typename S, typename R, bool DEV = false>
+template <typename S, typename R, int DEV = 0>
 void main_any(const Ctx& c, const void* src, void* dst, bool moments) {
     if (moments) main_s<S, R, true, DEV>(c, src, dst);
     else main_s<S, R, false, DEV>(c, src, dst);
 }
 
-template <typename S, bool DEV = false>
+template <typename S, int DEV = 0>
 void boundary_any(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
     hipLaunchKernelGGL((k_boundary<S, DEV>), dim3(nblocks), dim3(256), 0, c.stream,
                        static_cast<S*>(cur), b);
@@ -70,10 +70,10 @@ void init_any(const Ctx& c, const double* rw, const double* r0, const double* u0
         hipLaunchKernelGGL((k_psi_wall<R, EOS_NONE>), g, dim3(256), 0, c.stream, psiw, rw,
                            c.flags, c.nx, c.ny, c.pitch, ph);
     hipLaunchKernelGGL(k_init_scatter<S>, g, dim3(256), 0, c.stream, static_cast<S*>(buf),
-                       c.flags, r0, u0, v0, c.nx, c.ny, c.pitch, c.plane, c.ph.rref);
+                       c.flags, r0, u0, v0, c.nx, c.ny, c.pitch, c.plane, c.ph.rref, c.ref);
 }
 
-template <typename S, typename R, bool DEV>
+template <typename S, typename R, int DEV>
 void batch_any(const BatchLaunch& L) {
     hipLaunchKernelGGL((k_boundary_batch<S, DEV>), dim3(L.bnd_grid), dim3(256), 0, L.stream,
                        L.args);
@@ -88,7 +88,7 @@ void batch_any(const BatchLaunch& L) {
                            dim3(L.tile_w), 0, L.stream, L.args);
 }
 
-template <typename S, typename R, bool DEV>
+template <typename S, typename R, int DEV>
 int occupancy_any(int eos, int tile_w) {
     int n = 0;
     hipError_t e;

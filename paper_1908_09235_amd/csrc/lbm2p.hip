@@ -88,7 +88,9 @@ int default_tile_w(int nx) {
 }
 
 inline long long storage_bytes(int storage) {
-    return storage == LBM_STORE_F64 ? 8 : storage == LBM_STORE_F16DEV ? 2 : 4;
+    return storage == LBM_STORE_F64 ? 8
+           : (storage == LBM_STORE_F16DEV || storage == LBM_STORE_F16NODE) ? 2
+                                                                            : 4;
 }
 
 template <typename R>
@@ -135,6 +137,7 @@ Ctx ctx(lbm_domain* d) {
     c.side_f = d->side_f;
     c.partial = d->partial;
     c.mom_out = d->mom_out;
+    c.ref = nullptr;
     c.ph = d->ph64;
     c.stream = d->stream;
     return c;
@@ -161,6 +164,7 @@ BndArgs bnd_args(lbm_domain* d) {
     b.side_f = d->side_f;
     b.plane = d->plane;
     b.rref = d->ph64.rref;
+    b.lref = d->lref;
     b.fix = d->fix;
     b.partial = d->partial;
     b.np = d->nblocks;
@@ -261,7 +265,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (!(s->tau > 0.5) || !std::isfinite(s->tau)) return LBM_EINVAL;
     if (s->rule < 0 || s->rule > 5 || s->fix < 0 || s->fix > 3) return LBM_EINVAL;
     if (s->eos < 0 || s->eos > 2 || s->collision < 0 || s->collision > 1) return LBM_EINVAL;
-    if (s->storage < LBM_STORE_F64 || s->storage > LBM_STORE_F16DEV) return LBM_EINVAL;
+    if (s->storage < LBM_STORE_F64 || s->storage > LBM_STORE_F16NODE) return LBM_EINVAL;
     if (!(s->rho_ref >= 0.0) || !std::isfinite(s->rho_ref)) return LBM_EINVAL;
     if (s->reserved != 0) return LBM_EINVAL;
     if ((s->fix == LBM_FIX_B || s->fix == LBM_FIX_BAO) && s->rule != LBM_RULE_FH &&
@@ -284,7 +288,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         // 32-bit byte offsets
         const long long pitch = (nx + 63) / 64 * 64;
         const long long esz = storage_bytes(s->storage);
-        if (9 * (pitch * ny + 256) * esz >= (1LL << 32)) return LBM_EINVAL;
+        const long long extra = s->storage == LBM_STORE_F16NODE ? 4 * (pitch * ny + 256) : 0;
+        if (9 * (pitch * ny + 256) * esz + extra >= (1LL << 32)) return LBM_EINVAL;
     }
     const long long N = (long long)nx * ny;
     auto solid = [&](long long i) { return s->solid[i] != 0; };
@@ -517,9 +522,38 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->nslots = nslots;
     d->fallbacks = fallbacks;
 
+    std::vector<int> lref;
+    std::vector<float> rplane;  // FP16 per-node form: initial density plane
+    if (s->storage == LBM_STORE_F16NODE) {
+        // Each ghost (a solid node receiving incoming populations) is
+        // encoded against the density of one boundary node next to it: the
+        // first in table order, whose link records it.
+        std::vector<int> owner((size_t)P * ny, -1);
+        lref.assign(lnode.size(), 0);
+        for (size_t k = 0; k < lnode.size(); ++k) {
+            if (((lmeta[k] >> 4) & 15) == LK_PAD) continue;
+            const int g = lghost[k];
+            if (owner[g] < 0) {
+                owner[g] = (int)k;
+                lmeta[k] |= 1 << 16;
+            }
+            lref[k] = lslotb[owner[g]];
+        }
+        rplane.assign((size_t)d->plane, 0.0f);
+        for (long long i = 0; i < N; ++i)
+            if (!solid(i)) rplane[pidx((int)(i % nx), (int)(i / nx))] = float(s->rho0[i]);
+        for (size_t k = 0; k < lnode.size(); ++k)
+            if ((lmeta[k] >> 16) & 1) {
+                const int n = lnode[k];
+                rplane[lghost[k]] = float(s->rho0[(long long)(n / P) * nx + (n % P)]);
+            }
+    }
+
     // ---- device memory
     int rc;
-    const size_t fbytes = (size_t)9 * d->plane * d->esize;
+    d->fbytes = (size_t)9 * d->plane * d->esize +
+                (s->storage == LBM_STORE_F16NODE ? (size_t)4 * d->plane : 0);
+    const size_t fbytes = d->fbytes;
     if ((rc = dev_alloc(d, &d->f[0], fbytes))) return rc;
     if ((rc = dev_alloc(d, &d->f[1], fbytes))) return rc;
     if (hipMemsetAsync(d->f[0], 0, fbytes, d->stream) != hipSuccess) return LBM_EDEVICE;
@@ -548,6 +582,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &d->lslotf, lslotf))) return rc;
     if ((rc = upload(d, &d->lc, lc))) return rc;
     if ((rc = upload(d, &d->luw, luw))) return rc;
+    if (!lref.empty() && (rc = upload(d, &d->lref, lref))) return rc;
+
     const long long minus1 = -1;
     if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
         return LBM_EDEVICE;
@@ -568,7 +604,19 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &du0, u0))) return rc;
     if ((rc = upload(d, &dv0, v0))) return rc;
     if (d->storage == LBM_STORE_F64) launch_init_f64(ctx(d), drw, dr0, du0, dv0, d->f[1]);
-    else launch_init_f32(ctx(d), drw, dr0, du0, dv0, d->f[1]);
+    else {
+        Ctx c = ctx(d);
+        if (!rplane.empty()) {
+            // both buffers start with the initial density plane
+            const size_t off = (size_t)9 * d->plane * d->esize;
+            for (int k = 0; k < 2; ++k)
+                if (hipMemcpyAsync(static_cast<char*>(d->f[k]) + off, rplane.data(),
+                                   rplane.size() * 4, hipMemcpyHostToDevice, d->stream) != hipSuccess)
+                    return LBM_EDEVICE;
+            c.ref = reinterpret_cast<const float*>(static_cast<char*>(d->f[1]) + off);
+        }
+        launch_init_f32(c, drw, dr0, du0, dv0, d->f[1]);
+    }
     launch_main(d, d->f[1], d->f[0], false);
     d->cur = 0;
     d->t = 0;
@@ -780,7 +828,7 @@ int lbm_unstable_step(lbm_domain* d, int64_t* step) {
 }
 
 static size_t state_bytes(const lbm_domain* d) {
-    return 8 * 4 + 2 * (size_t)9 * d->plane * d->esize + (size_t)3 * std::max(d->nslots, 1) * 8 +
+    return 8 * 4 + 2 * d->fbytes + (size_t)3 * std::max(d->nslots, 1) * 8 +
            (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8 + (size_t)d->cap * 8 + 8;
 }
 
@@ -798,7 +846,7 @@ int lbm_get_state(lbm_domain* d, void* buf, size_t* bytes) {
                              (uint64_t)d->storage};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
-    const size_t fb = (size_t)9 * d->plane * d->esize;
+    const size_t fb = d->fbytes;
     const size_t sm = (size_t)3 * std::max(d->nslots, 1) * 8;
     const size_t sf = (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8;
     if (hipMemcpy(p, d->f[d->cur], fb, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
@@ -827,7 +875,7 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
         return LBM_EINVAL;
     p += sizeof(hdr);
     if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
-    const size_t fb = (size_t)9 * d->plane * d->esize;
+    const size_t fb = d->fbytes;
     const size_t sm = (size_t)3 * std::max(d->nslots, 1) * 8;
     const size_t sf = (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8;
     d->cur = 0;

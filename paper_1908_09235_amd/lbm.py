@@ -20,7 +20,7 @@ RULE = {"halfway": 0, "fh": 1, "mls": 2, "ibb_linear": 3, "ibb_quadratic": 4,
 FIX = {"none": 0, "A": 1, "B": 2, "bao": 3}
 EOS = {"none": 0, "exp": 1, "cs": 2}
 COLL = {"bgk": 0, "mrt": 1}
-STORAGE = {"f64": 0, "f32": 1, "f32_arith32": 2, "f32dev": 3, "f16dev": 4}
+STORAGE = {"f64": 0, "f32": 1, "f32_arith32": 2, "f32dev": 3, "f16dev": 4, "f16node": 5}
 
 LINK_NP = np.dtype([("x", "<i4"), ("y", "<i4"), ("dir", "<i4"),
                     ("reserved", "<i4"), ("q", "<f8"), ("uwx", "<f8"),

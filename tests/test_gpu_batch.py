@@ -50,7 +50,8 @@ def same(a, b):
 
 
 @pytest.mark.parametrize("storage,persistent,graph", [
-    ("f64", 1, 0), ("f64", 0, 8), ("f32", 1, 8), ("f32dev", 1, 0), ("f16dev", 0, 0)])
+    ("f64", 1, 0), ("f64", 0, 8), ("f32", 1, 8), ("f32dev", 1, 0), ("f16dev", 0, 0),
+    ("f16node", 1, 8)])
 def test_batch_equals_alone(L, storage, persistent, graph):
     probs = small_mix(6)
     steps = 120

@@ -269,3 +269,47 @@ def test_full_size_2048_properties(L, storage):
         e = [rel_err((r, ux, uy)[i], _ORACLE[key][i], fl) for i in range(3)]
         say(f"    fp32 vs fp64 {e}")
         assert max(e) < 1e-4
+
+
+def _couette_error(p, ux, uy):
+    m = p.meta
+    Y, X = np.mgrid[0:p.ny, 0:p.nx].astype(float)
+    dx, dy = X - m["c"], Y - m["c"]
+    r = np.maximum(np.hypot(dx, dy), 1e-9)
+    r1, r2, U = m["r1"], m["r2"], m["U"]
+    ut = U * r1 * (r2 ** 2 / r - r) / (r2 ** 2 - r1 ** 2)
+    ax, ay = -ut * dy / r, ut * dx / r
+    fl = ~p.solid.astype(bool)
+    return float(np.sqrt(((ux - ax) ** 2 + (uy - ay) ** 2)[fl].sum() / (ax ** 2 + ay ** 2)[fl].sum()))
+
+
+@pytest.mark.parametrize("fix", ["none", "A", "B"])
+def test_couette_convergence_on_gpu(L, fix):
+    """Circular Couette flow, r1 = 10, 20, 40, 80 (r2 = 2 r1, inner wall at
+    surface speed 0.01), MLS, FP64, from rest to steady state: L2 error of
+    the velocity against the analytic profile and its order.  The moving
+    wall's momentum term changes the mass in every scheme (A and B correct
+    only the rule's own leak); the change is reported."""
+    errs = []
+    for r1 in (10, 20, 40, 80):
+        p = cfg.couette(r1, rule="mls", fix=fix, tau=0.8)
+        steps = int(60 * r1 * r1)  # several viscous times (r2 - r1)^2 / nu
+        with L.Domain(p, history_capacity=1 << 10) as d:
+            m0 = d.total_mass()
+            d.step(steps)
+            _, ux, uy = d.moments()
+            d.step(1000)
+            _, ux2, uy2 = d.moments()
+            du = float(np.max(np.abs(ux2 - ux)) + np.max(np.abs(uy2 - uy))) / 0.01
+            drift = abs(d.total_mass() - m0) / m0
+        e = _couette_error(p, ux2, uy2)
+        errs.append(e)
+        say(f"    {fix} r1={r1}: steps {steps + 1000}, L2 error {e:.3e}, "
+            f"change over the last 1000 steps {du:.1e} U, mass change {drift:.1e}")
+        assert du < 1e-9  # steady
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    mean = np.log2(errs[0] / errs[-1]) / 3
+    say(f"    {fix}: orders {np.round(orders, 2)}, mean {mean:.2f}")
+    assert np.all(np.diff(errs) < 0)
+    if fix == "none":
+        assert np.all(orders > 1.5) and 1.7 < mean < 2.5
