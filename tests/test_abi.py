@@ -110,7 +110,7 @@ def test_bad_launch_shape_and_storage_are_rejected(L):
         assert e.value.code == L.LBM_EINVAL
     d, keep = L.make_desc(p)
     h = ctypes.c_void_p()
-    for st in (-1, 5, 7):
+    for st in (-1, 6, 7):
         d.storage = st
         assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
     d.storage = L.STORAGE["f16dev"]
