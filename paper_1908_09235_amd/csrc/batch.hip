@@ -75,7 +75,7 @@ struct lbm_batch {
     int* h_small = nullptr;  // qbound[9], nlblk
 
     hipGraphExec_t graph = nullptr;
-    int graph_key[4] = {0, 0, 0, 0};  // tile_w, persistent, main grid, steps
+    int graph_key[5] = {0, 0, 0, 0, 0};  // tile_w, persistent, main grid, steps, save_f
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -168,8 +168,10 @@ BInst make_inst(lbm_domain* d) {
     I.f[0] = d->f[0];
     I.f[1] = d->f[1];
     I.flags = d->flags;
-    I.psiw = d->psiw;
+    I.side_mom_bytes = (unsigned)(3 * std::max(d->nslots, 1) * 8);
+    I.side_f_bytes = (unsigned)(9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8);
     I.side_idx = d->side_idx;
+    I.psiw = d->psiw;
     I.side_mom = d->side_mom;
     I.side_f = d->side_f;
     I.partial = d->partial;
@@ -264,10 +266,13 @@ BatchLaunch launch_of(lbm_batch* b) {
     L.eos = b->bd.eos;
     L.storage = b->bd.storage;
     L.tile_w = b->tile_w;
+    L.save_f = false;
+    for (lbm_domain* d : b->inst)
+        if (d && d->save_f) L.save_f = true;
     if (b->persistent) {
         const int occ = b->bd.storage == LBM_STORE_F64
-                            ? batch_occupancy_f64(b->bd.eos, b->bd.storage, b->tile_w)
-                            : batch_occupancy_f32(b->bd.eos, b->bd.storage, b->tile_w);
+                            ? batch_occupancy_f64(b->bd.eos, b->bd.storage, b->tile_w, L.save_f)
+                            : batch_occupancy_f32(b->bd.eos, b->bd.storage, b->tile_w, L.save_f);
         L.main_grid = b->ncu * std::max(occ, 1);
     } else {
         L.main_grid = (int)std::max<long long>(b->ntiles, 1);
@@ -296,7 +301,7 @@ int enqueue(lbm_batch* b, long long n) {
     const int G = b->graph_steps;
     long long done = 0;
     if (G > 0 && n >= G) {
-        const int key[4] = {b->tile_w, b->persistent, L.main_grid, G};
+        const int key[5] = {b->tile_w, b->persistent, L.main_grid, G, L.save_f ? 1 : 0};
         if (b->graph && std::memcmp(key, b->graph_key, sizeof key) != 0) drop_graph(b);
         if (!b->graph) {
             hipGraph_t g = nullptr;

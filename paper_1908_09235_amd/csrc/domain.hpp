@@ -47,7 +47,7 @@ struct lbm_domain {
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     uint8_t* flags = nullptr;
-    void* psiw = nullptr;
+    float* psiw = nullptr;  // FP16 storage: psi_w of solid nodes in FP32
     int* side_idx = nullptr;
     double* side_mom = nullptr;
     double* side_f = nullptr;

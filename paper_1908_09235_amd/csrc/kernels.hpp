@@ -49,8 +49,8 @@ struct MainArgs {
     const S* __restrict__ src;
     S* __restrict__ dst;
     const uint8_t* __restrict__ flags;  // per node (pitch layout)
-    const void* __restrict__ psiw;      // per node, compute type, solid only
     const int* __restrict__ side_idx;   // per node, flagged only
+    const float* __restrict__ psiw;     // FP16 storage: psi_w of solid nodes
     double* __restrict__ side_mom;      // [slot][3]: rho, ux, uy
     double* __restrict__ side_f;        // [slot][9]: pre-collision f
     double* __restrict__ partial;       // per workgroup
@@ -58,6 +58,7 @@ struct MainArgs {
     int nx, ny, pitch;
     long long plane;                    // elements per population plane
     int tile_h, nsegs, nstrips;
+    unsigned side_mom_bytes, side_f_bytes;
 };
 
 // Buffer resources: a 32-bit byte range on an SGPR base, so that a load
@@ -69,8 +70,16 @@ constexpr int kRsrcWord3 = 0x00020000;
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kRsrcWord3);
 }
+// A lane offset at or beyond every buffer's range: the access is dropped.
+// Buffers stay below kOOB bytes.
+constexpr unsigned kOOB = 0xFFFFFF00u;
+
 template <typename T>
 __device__ __forceinline__ T bload(rsrc_t r, unsigned v, unsigned s);
+template <>
+__device__ __forceinline__ int bload<int>(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+}
 template <>
 __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned v, unsigned s) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
@@ -108,9 +117,10 @@ __device__ __forceinline__ R dens(const R f[9]) {
 template <typename S, typename R, int NR>
 struct RowLoad {
     S f[9];
-    R pw;
     uint8_t fl;
-    float rr[NR];  // per-node references of the nine source nodes (DEV 2)
+    int si;        // side slot (boundary nodes)
+    float rr[NR];  // densities of the nine source nodes (DEV 2)
+    float pw;      // FP16 storage: psi_w of a solid node in FP32
 };
 
 // Columns a strip updates: a workgroup of tile_w lanes also pulls the
@@ -125,12 +135,22 @@ __host__ __device__ constexpr int strip_cols(int tile_w) { return tile_w - 2; }
 // from one reference density; 2 as deviations g = f - w r(x) from the
 // density r(x) of the node x whose slot holds g, kept in an FP32 plane
 // after the nine population planes of each buffer.
-template <typename S, typename R, int EOS, bool MOMENTS, int DEV>
+// SAVEF: boundary nodes also save their pre-collision populations.
+//
+// Every lane issues every load and store of every row, so the number of
+// memory operations in flight is the same on all paths and the waits
+// before a use are exact: the rows in flight keep streaming while a row is
+// computed.  A lane with nothing to move passes an offset beyond the
+// buffer's range, which the hardware drops (no memory access; a load
+// returns 0).  Solid nodes keep psi of their wall density in their own
+// rest slot (plane 0), which nothing else reads or writes; with FP16
+// storage it is read in FP32 from a per-node array instead.
+template <typename S, typename R, int EOS, bool MOMENTS, int DEV, bool SAVEF>
 __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& ph,
                                           int tile) {
     __shared__ R ring[4][kMaxTileW];
     __shared__ double wsum[kMaxTileW / 64];
-    constexpr unsigned ES = sizeof(S), RS = sizeof(R);
+    constexpr unsigned ES = sizeof(S);
     constexpr int NR = DEV == 2 ? 9 : 1;
     const unsigned pitch = (unsigned)a.pitch;
     // one resource per buffer; plane and row offsets go in the scalar
@@ -140,7 +160,10 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     const rsrc_t rs = make_rsrc(a.src, bbytes);
     const rsrc_t rd = make_rsrc(a.dst, bbytes);
     const rsrc_t rfl = make_rsrc(a.flags, pitch * (unsigned)a.ny);
-    const rsrc_t rpw = make_rsrc(a.psiw, pitch * (unsigned)a.ny * RS);
+    const rsrc_t rsi = make_rsrc(a.side_idx, pitch * (unsigned)a.ny * 4u);
+    const rsrc_t rsm = make_rsrc(a.side_mom, a.side_mom_bytes);
+    const rsrc_t rsf = make_rsrc(a.side_f, a.side_f_bytes);
+    const rsrc_t rpw = make_rsrc(a.psiw, ES == 2 ? pitch * (unsigned)a.ny * 4u : 0u);
     // DEV 2: the FP32 density plane follows the nine population planes
     const unsigned rbase = 9u * pb;
 
@@ -168,54 +191,63 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     const int ystart = dir > 0 ? y0 : y0 + H - 1;
     auto row_of = [&](int k) {
         int y = ystart + dir * k;
-        return y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
+        y = y < 0 ? y + a.ny : y;
+        y = y >= a.ny ? y - a.ny : y;
+        return y;
     };
 
     // flags of the next row to issue are loaded one issue ahead
     uint8_t nfl;
     auto load_flags = [&](int k) {
-        const unsigned r = (unsigned)row_of(k) * pitch;
-        nfl = bload<uint8_t>(rfl, x, r);
+        nfl = bload<uint8_t>(rfl, x, (unsigned)row_of(k) * pitch);
     };
-    auto pull = [&](S f[9], R& pw, float rr[NR], uint8_t fl, unsigned c, unsigned cm,
-                    unsigned cp, unsigned rm, unsigned r0, unsigned rp, unsigned prow) {
-        if (fl & FL_SOLID) {
-            pw = bload<R>(rpw, c * RS, prow);
-        } else {
-            if constexpr (DEV == 2) {
-                // the source nodes' densities, rows of the FP32 plane
-                const unsigned qm = rbase + rm / ES * 4u, q0 = rbase + r0 / ES * 4u,
-                               qp = rbase + rp / ES * 4u;
-                rr[0] = bload<float>(rs, c * 4u, q0);
-                rr[1 % NR] = bload<float>(rs, cm * 4u, q0);
-                rr[2 % NR] = bload<float>(rs, c * 4u, qm);
-                rr[3 % NR] = bload<float>(rs, cp * 4u, q0);
-                rr[4 % NR] = bload<float>(rs, c * 4u, qp);
-                rr[5 % NR] = bload<float>(rs, cm * 4u, qm);
-                rr[6 % NR] = bload<float>(rs, cp * 4u, qm);
-                rr[7 % NR] = bload<float>(rs, cp * 4u, qp);
-                rr[8 % NR] = bload<float>(rs, cm * 4u, qp);
-            }
-            f[0] = bload<S>(rs, c * ES, r0);
-            f[1] = bload<S>(rs, cm * ES, 1 * pb + r0);
-            f[2] = bload<S>(rs, c * ES, 2 * pb + rm);
-            f[3] = bload<S>(rs, cp * ES, 3 * pb + r0);
-            f[4] = bload<S>(rs, c * ES, 4 * pb + rp);
-            f[5] = bload<S>(rs, cm * ES, 5 * pb + rm);
-            f[6] = bload<S>(rs, cp * ES, 6 * pb + rm);
-            f[7] = bload<S>(rs, cp * ES, 7 * pb + rp);
-            f[8] = bload<S>(rs, cm * ES, 8 * pb + rp);
-        }
-    };
+    // rows -1 .. H are pulled (the outer two for psi only); later ones only
+    // keep the pipeline uniform and move nothing
     auto issue = [&](int k, RowLoad<S, R, NR>& L) {
         const int y = row_of(k);
-        L.fl = act ? nfl : uint8_t(FL_SOLID);  // idle lanes load nothing
+        const bool rv = k <= H;
+        const uint8_t fl = (act && rv) ? nfl : uint8_t(FL_SOLID);
+        L.fl = fl;
         load_flags(k + 1);
+        const bool own = act && rv, fluid = !(fl & FL_SOLID);
         const unsigned r0 = (unsigned)y * pitch * ES;
         const unsigned rm = (unsigned)(y == 0 ? a.ny - 1 : y - 1) * pitch * ES;
         const unsigned rp = (unsigned)(y == a.ny - 1 ? 0 : y + 1) * pitch * ES;
-        const unsigned prow = (unsigned)y * pitch * RS;
-        if (act) pull(L.f, L.pw, L.rr, L.fl, x, xm, xp, rm, r0, rp, prow);
+        const unsigned vc = fluid ? x * ES : kOOB, vm = fluid ? xm * ES : kOOB,
+                       vp = fluid ? xp * ES : kOOB;
+        // plane 0 of the node itself: the rest population, or psi_w if solid
+        L.f[0] = bload<S>(rs, own ? x * ES : kOOB, r0);
+        L.f[1] = bload<S>(rs, vm, 1 * pb + r0);
+        L.f[2] = bload<S>(rs, vc, 2 * pb + rm);
+        L.f[3] = bload<S>(rs, vp, 3 * pb + r0);
+        L.f[4] = bload<S>(rs, vc, 4 * pb + rp);
+        L.f[5] = bload<S>(rs, vm, 5 * pb + rm);
+        L.f[6] = bload<S>(rs, vp, 6 * pb + rm);
+        L.f[7] = bload<S>(rs, vp, 7 * pb + rp);
+        L.f[8] = bload<S>(rs, vm, 8 * pb + rp);
+        if constexpr (DEV == 2) {
+            // the source nodes' densities, rows of the FP32 plane
+            const unsigned qm = rbase + rm / ES * 4u, q0 = rbase + r0 / ES * 4u,
+                           qp = rbase + rp / ES * 4u;
+            const unsigned wc = fluid ? x * 4u : kOOB, wm = fluid ? xm * 4u : kOOB,
+                           wp = fluid ? xp * 4u : kOOB;
+            L.rr[0] = bload<float>(rs, wc, q0);
+            L.rr[1 % NR] = bload<float>(rs, wm, q0);
+            L.rr[2 % NR] = bload<float>(rs, wc, qm);
+            L.rr[3 % NR] = bload<float>(rs, wp, q0);
+            L.rr[4 % NR] = bload<float>(rs, wc, qp);
+            L.rr[5 % NR] = bload<float>(rs, wm, qm);
+            L.rr[6 % NR] = bload<float>(rs, wp, qm);
+            L.rr[7 % NR] = bload<float>(rs, wp, qp);
+            L.rr[8 % NR] = bload<float>(rs, wm, qp);
+        }
+        if constexpr (ES == 2)
+            L.pw = bload<float>(rpw, (own && !fluid) ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
+        if constexpr (!MOMENTS) {
+            // side slot of a boundary node (or of an x_f node of MLS)
+            const bool side = fluid && (fl & (FL_SAVE_MOM | FL_SAVE_F));
+            L.si = bload<int>(rsi, side ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
+        }
     };
     // stored form -> populations (DEV 2) or the stored form itself
     auto decode = [&](const RowLoad<S, R, NR>& L, R f[9]) {
@@ -223,119 +255,114 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         for (int q = 0; q < 9; ++q)
             f[q] = DEV == 2 ? R(L.f[q]) + R(wt(q)) * R(L.rr[q % NR]) : R(L.f[q]);
     };
-    auto psi_node = [&](const RowLoad<S, R, NR>& L) {
+    auto publish = [&](const RowLoad<S, R, NR>& L, int slot) {
         R f[9];
         decode(L, f);
         const R rho = DEV == 1 ? ph.rref + dens<R>(f) : dens<R>(f);
-        return (L.fl & FL_SOLID) ? L.pw : psi_of<EOS, R>(rho, ph);
-    };
-    auto publish = [&](const RowLoad<S, R, NR>& L, int slot) {
-        if (act) ring[slot][tid] = psi_node(L);
+        const R pw = ES == 2 ? R(L.pw) : R(L.f[0]);
+        ring[slot][tid] = (L.fl & FL_SOLID) ? pw : psi_of<EOS, R>(rho, ph);
     };
 
     double msum = 0.0;
     // row k: collide with psi of rows k-1, k, k+1; then prefetch row k+3
-    auto step = [&](int k, RowLoad<S, R, NR>& Lc, RowLoad<S, R, NR>& Ln, RowLoad<S, R, NR>& Lf) {
+    auto step = [&](int k, RowLoad<S, R, NR>& Lc, RowLoad<S, R, NR>& Ln) {
         const int y = row_of(k);
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
         const int sym = dir > 0 ? sm : sp, syp = dir > 0 ? sp : sm;
         publish(Ln, sp);
         __syncthreads();
-        if (upd && !(Lc.fl & FL_SOLID)) {
-            R fc[9];  // f, or (DEV 1) the deviations g
-            decode(Lc, fc);
-            const int c = tid;
-            const R drho = dens<R>(fc);
-            const R rho = DEV == 1 ? ph.rref + drho : drho;
-            const R irho = rcp(rho);
-            R Fx = R(0), Fy = R(0);
-            if constexpr (EOS != EOS_NONE) {
-                // Eq. (16): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, with
-                // opposite neighbours paired
-                const R p1 = ring[s0][c + 1], p3 = ring[s0][c - 1];
-                const R p2 = ring[syp][c], p4 = ring[sym][c];
-                const R p5 = ring[syp][c + 1], p6 = ring[syp][c - 1];
-                const R p7 = ring[sym][c - 1], p8 = ring[sym][c + 1];
-                const R w1 = R(wf(1)), w5 = R(wf(5));
-                const R sx = w1 * (p1 - p3) + w5 * ((p5 - p7) + (p8 - p6));
-                const R sy = w1 * (p2 - p4) + w5 * ((p5 - p7) + (p6 - p8));
-                const R g = -ph.G * ring[s0][c];
-                Fx = g * sx;
-                Fy = g * sy;
-            }
-            Fx += rho * ph.gx;
-            Fy += rho * ph.gy;
-            // Eq. (5)
-            const R mx = (fc[1] - fc[3]) + ((fc[5] - fc[7]) + (fc[8] - fc[6]));
-            const R my = (fc[2] - fc[4]) + ((fc[5] - fc[7]) + (fc[6] - fc[8]));
-            const R ux = (mx + R(0.5) * Fx) * irho;
-            const R uy = (my + R(0.5) * Fy) * irho;
-            if constexpr (MOMENTS) {
+        const bool live = upd && k < H && !(Lc.fl & FL_SOLID);
+        R fc[9];  // f, or (DEV 1) the deviations g
+        decode(Lc, fc);
+        const int c = tid;
+        const R drho = dens<R>(fc);
+        const R rho = DEV == 1 ? ph.rref + drho : drho;
+        const R irho = rcp(rho);
+        R Fx = R(0), Fy = R(0);
+        if constexpr (EOS != EOS_NONE) {
+            // Eq. (16): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, with
+            // opposite neighbours paired
+            const int cl = c > 0 ? c - 1 : 0, cr = c < W - 1 ? c + 1 : W - 1;
+            const R p1 = ring[s0][cr], p3 = ring[s0][cl];
+            const R p2 = ring[syp][c], p4 = ring[sym][c];
+            const R p5 = ring[syp][cr], p6 = ring[syp][cl];
+            const R p7 = ring[sym][cl], p8 = ring[sym][cr];
+            const R w1 = R(wf(1)), w5 = R(wf(5));
+            const R sx = w1 * (p1 - p3) + w5 * ((p5 - p7) + (p8 - p6));
+            const R sy = w1 * (p2 - p4) + w5 * ((p5 - p7) + (p6 - p8));
+            const R g = -ph.G * ring[s0][c];
+            Fx = g * sx;
+            Fy = g * sy;
+        }
+        Fx += rho * ph.gx;
+        Fy += rho * ph.gy;
+        // Eq. (5)
+        const R mx = (fc[1] - fc[3]) + ((fc[5] - fc[7]) + (fc[8] - fc[6]));
+        const R my = (fc[2] - fc[4]) + ((fc[5] - fc[7]) + (fc[6] - fc[8]));
+        const R ux = (mx + R(0.5) * Fx) * irho;
+        const R uy = (my + R(0.5) * Fy) * irho;
+        if constexpr (MOMENTS) {
+            if (upd && k < H) {
+                const bool fl = live;
                 const long long o = (long long)y * a.nx + x;
                 const long long n2 = (long long)a.nx * a.ny;
-                a.mom_out[o] = DEV == 1 ? double(ph.rref) + double(drho) : double(rho);
-                a.mom_out[n2 + o] = double(ux);
-                a.mom_out[2 * n2 + o] = double(uy);
-            } else {
-                // FP64 density (the deviation forms add the reference here)
-                double rho_d = DEV == 1 ? double(ph.rref) + double(drho) : double(rho);
-                if constexpr (DEV == 2) {
-                    rho_d = 0.0;
-#pragma unroll
-                    for (int q = 0; q < 9; ++q)
-                        rho_d += double(Lc.f[q]) + wt(q) * double(Lc.rr[q % NR]);
-                }
-                msum += rho_d;
-                if (Lc.fl & (FL_SAVE_MOM | FL_SAVE_F)) {
-                    const int slot = a.side_idx[(unsigned)y * pitch + x];
-                    if (Lc.fl & FL_SAVE_MOM) {
-                        a.side_mom[3 * slot + 0] = rho_d;
-                        a.side_mom[3 * slot + 1] = double(ux);
-                        a.side_mom[3 * slot + 2] = double(uy);
-                    }
-                    if (Lc.fl & FL_SAVE_F) {
-#pragma unroll
-                        for (int q = 0; q < 9; ++q)
-                            a.side_f[9 * slot + q] = DEV == 1
-                                                             ? double(fc[q]) + wt(q) * double(ph.rref)
-                                                             : double(fc[q]);
-                    }
-                }
-                R dh[9];
-                collide<R>(fc, rho, drho, ux, uy, Fx, Fy, ph, dh);
-                const unsigned r0 = (unsigned)y * pitch * ES;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    // DEV 2: re-encoded against this node's density,
-                    // g* = g + w (r(x - e) - rho) + dh, without forming f
-                    const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(Lc.rr[q % NR]) - rho)) + dh[q]
-                                         : fc[q] + dh[q];
-                    bstore(S(v), rd, x * ES, q * pb + r0);
-                }
-                if constexpr (DEV == 2) bstore(float(rho), rd, x * 4u, rbase + (unsigned)y * pitch * 4u);
+                a.mom_out[o] = fl ? (DEV == 1 ? double(ph.rref) + double(drho) : double(rho)) : 0.0;
+                a.mom_out[n2 + o] = fl ? double(ux) : 0.0;
+                a.mom_out[2 * n2 + o] = fl ? double(uy) : 0.0;
             }
-        } else if (MOMENTS && upd) {
-            const long long o = (long long)y * a.nx + x;
-            const long long n2 = (long long)a.nx * a.ny;
-            a.mom_out[o] = 0.0;
-            a.mom_out[n2 + o] = 0.0;
-            a.mom_out[2 * n2 + o] = 0.0;
+        } else {
+            // FP64 density (the deviation forms add the reference here)
+            double rho_d = DEV == 1 ? double(ph.rref) + double(drho) : double(rho);
+            if constexpr (DEV == 2) {
+                rho_d = 0.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) rho_d += double(Lc.f[q]) + wt(q) * double(Lc.rr[q % NR]);
+            }
+            msum += live ? rho_d : 0.0;
+            // moments of boundary nodes (and pre-collision populations)
+            const unsigned so = (live && (Lc.fl & FL_SAVE_MOM)) ? (unsigned)Lc.si * 24u : kOOB;
+            bstore(rho_d, rsm, so, 0u);
+            bstore(double(ux), rsm, so + 8u, 0u);
+            bstore(double(uy), rsm, so + 16u, 0u);
+            if constexpr (SAVEF) {
+                const unsigned fo = (live && (Lc.fl & FL_SAVE_F)) ? (unsigned)Lc.si * 72u : kOOB;
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+                    bstore(DEV == 1 ? double(fc[q]) + wt(q) * double(ph.rref) : double(fc[q]), rsf,
+                           fo + 8u * q, 0u);
+            }
+            R dh[9];
+            collide<R>(fc, rho, drho, ux, uy, Fx, Fy, ph, dh);
+            const unsigned r0 = (unsigned)y * pitch * ES;
+            const unsigned vo = live ? x * ES : kOOB;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                // DEV 2: re-encoded against this node's density,
+                // g* = g + w (r(x - e) - rho) + dh, without forming f
+                const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(Lc.rr[q % NR]) - rho)) + dh[q]
+                                     : fc[q] + dh[q];
+                bstore(S(v), rd, vo, q * pb + r0);
+            }
+            if constexpr (DEV == 2)
+                bstore(float(rho), rd, live ? x * 4u : kOOB, rbase + (unsigned)y * pitch * 4u);
         }
-        if (k + 3 <= H) issue(k + 3, Lc);  // Lc is free again
+        issue(k + 3, Lc);  // Lc is free again
     };
 
     RowLoad<S, R, NR> A, B, C;
     load_flags(-1);
     issue(-1, C);
-    publish(C, 0);
     issue(0, A);
     issue(1, B);
+    publish(C, 0);
+    issue(2, C);
     publish(A, 1);
-    if (H > 1) issue(2, C);
-    for (int k = 0; k < H; k += 3) {
-        step(k, A, B, C);
-        if (k + 1 < H) step(k + 1, B, C, A);
-        if (k + 2 < H) step(k + 2, C, A, B);
+    // a whole number of three-row rotations; rows k >= H store nothing
+    const int H3 = (H + 2) / 3 * 3;
+    for (int k = 0; k < H3; k += 3) {
+        step(k, A, B);
+        step(k + 1, B, C);
+        step(k + 2, C, A);
     }
 
     if constexpr (!MOMENTS) {
@@ -352,9 +379,9 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     }
 }
 
-template <typename S, typename R, int EOS, bool MOMENTS, int DEV>
+template <typename S, typename R, int EOS, bool MOMENTS, int DEV, bool SAVEF>
 __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
-    main_tile<S, R, EOS, MOMENTS, DEV>(a, ph, xcd_tile(blockIdx.x, gridDim.x));
+    main_tile<S, R, EOS, MOMENTS, DEV, SAVEF>(a, ph, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Sum the main kernel's partials in a fixed order into the history ring.
@@ -607,16 +634,23 @@ __global__ void k_init_scatter(S* __restrict__ B, const uint8_t* __restrict__ fl
     }
 }
 
-// psi of the virtual wall density at solid nodes
-template <typename R, int EOS>
-__global__ void k_psi_wall(R* __restrict__ psiw, const double* __restrict__ rho_wall,
+// psi of the virtual wall density, kept in the rest slot (plane 0) of each
+// solid node in both buffers
+template <typename S, typename R, int EOS>
+__global__ void k_psi_wall(S* __restrict__ b0, S* __restrict__ b1, float* __restrict__ pw32,
+                           const double* __restrict__ rho_wall,
                            const uint8_t* __restrict__ flags, int nx, int ny,
                            int pitch, Phys<R> ph) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= nx || y >= ny) return;
     const int i = y * pitch + x;
-    psiw[i] = (flags[i] & FL_SOLID) ? psi_of<EOS, R>(R(rho_wall[y * nx + x]), ph) : R(0);
+    if (flags[i] & FL_SOLID) {
+        const R p = psi_of<EOS, R>(R(rho_wall[y * nx + x]), ph);
+        b0[i] = S(p);
+        b1[i] = S(p);
+        if (pw32) pw32[i] = float(p);
+    }
 }
 
 // ---------------------------------------------------------------- batches
@@ -631,12 +665,13 @@ __global__ void k_psi_wall(R* __restrict__ psiw, const double* __restrict__ rho_
 struct BInst {
     void* f[2];  // state buffers; f[t & 1] holds f*(t)
     const uint8_t* flags;
-    const void* psiw;
     const int* side_idx;
+    const float* psiw;
     double* side_mom;
     double* side_f;
     double* partial;  // one FP64 mass partial per tile
     int nx, ny, pitch, nsegs, nstrips, np;
+    unsigned side_mom_bytes, side_f_bytes;
     long long plane;
     Phys<double> ph;
     // boundary tables (see BndArgs)
@@ -677,8 +712,8 @@ __device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long 
     a.src = static_cast<const S*>(I.f[c]);
     a.dst = static_cast<S*>(I.f[c ^ 1]);
     a.flags = I.flags;
-    a.psiw = I.psiw;
     a.side_idx = I.side_idx;
+    a.psiw = I.psiw;
     a.side_mom = I.side_mom;
     a.side_f = I.side_f;
     a.partial = I.partial;
@@ -690,17 +725,19 @@ __device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long 
     a.tile_h = tile_h;
     a.nsegs = I.nsegs;
     a.nstrips = I.nstrips;
+    a.side_mom_bytes = I.side_mom_bytes;
+    a.side_f_bytes = I.side_f_bytes;
     return a;
 }
 
-template <typename S, typename R, int EOS, int DEV>
+template <typename S, typename R, int EOS, int DEV, bool SAVEF>
 __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
     g = __builtin_amdgcn_readfirstlane(g);
     const int2 te = b.tiles[g];
     const BState st = b.state[te.x];
     if (st.remaining <= 0) return;
     const BInst& I = b.inst[te.x];
-    main_tile<S, R, EOS, false, DEV>(inst_main_args<S>(I, st.t, b.tile_h), phys_as<R>(I.ph),
+    main_tile<S, R, EOS, false, DEV, SAVEF>(inst_main_args<S>(I, st.t, b.tile_h), phys_as<R>(I.ph),
                                      te.y);
 }
 
@@ -709,10 +746,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
 // the other queues in turn, until all are empty.  The queues hold
 // contiguous runs of the tile list, so one XCD works through compact
 // pieces of the same instances and finds their halos in its L2.
-template <typename S, typename R, int EOS, int DEV>
+template <typename S, typename R, int EOS, int DEV, bool SAVEF>
 __global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
     if (!b.persistent) {
-        batch_tile<S, R, EOS, DEV>(b, xcd_tile(blockIdx.x, gridDim.x));
+        batch_tile<S, R, EOS, DEV, SAVEF>(b, xcd_tile(blockIdx.x, gridDim.x));
         return;
     }
     __shared__ int s_g;
@@ -736,7 +773,7 @@ __global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
         __syncthreads();
         const int g = s_g;
         if (g < 0) break;
-        batch_tile<S, R, EOS, DEV>(b, g);
+        batch_tile<S, R, EOS, DEV, SAVEF>(b, g);
     }
 }
 

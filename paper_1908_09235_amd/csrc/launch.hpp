@@ -16,10 +16,12 @@ struct Ctx {
     int storage;  // lbm_storage
     int tile_w, tile_h, nsegs, nstrips, nblocks;
     const uint8_t* flags;
-    void* psiw;
+    float* psiw;  // FP16 storage: psi_w of solid nodes in FP32 (else null)
     const int* side_idx;
     double* side_mom;
     double* side_f;
+    unsigned side_mom_bytes, side_f_bytes;
+    bool save_f;  // boundary nodes save pre-collision populations (Zhao-Yong)
     double* partial;
     double* mom_out;
     const float* ref;  // init: density plane of the buffer being filled (or null)
@@ -33,11 +35,12 @@ void launch_main_f32(const Ctx& c, const void* src, void* dst, bool moments);
 // one boundary pass on cur
 void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
 void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
-// psi at walls and f(0) = f_eq(rho0, u0) scattered into buf
+// psi at walls into plane 0 of both buffers, and f(0) = f_eq(rho0, u0)
+// scattered into buf
 void launch_init_f64(const Ctx& c, const double* rho_wall, const double* rho0,
-                     const double* ux0, const double* uy0, void* buf);
+                     const double* ux0, const double* uy0, void* buf, void* other);
 void launch_init_f32(const Ctx& c, const double* rho_wall, const double* rho0,
-                     const double* ux0, const double* uy0, void* buf);
+                     const double* ux0, const double* uy0, void* buf, void* other);
 void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
                    long long* unstable);
 
@@ -48,6 +51,7 @@ struct BatchLaunch {
     int eos, storage;
     int tile_w;     // main-pass workgroup size
     int main_grid;  // persistent: workgroups; otherwise: tiles
+    bool save_f;    // some instance saves pre-collision populations
     int bnd_grid;
     int red_grid;
     hipStream_t stream;
@@ -56,7 +60,7 @@ void launch_batch_f64(const BatchLaunch& L);
 void launch_batch_f32(const BatchLaunch& L);
 void launch_batch_reduce(const BatchLaunch& L);
 // resident workgroups per CU of the batched main kernel
-int batch_occupancy_f64(int eos, int storage, int tile_w);
-int batch_occupancy_f32(int eos, int storage, int tile_w);
+int batch_occupancy_f64(int eos, int storage, int tile_w, bool save_f);
+int batch_occupancy_f32(int eos, int storage, int tile_w, bool save_f);
 
 }  // namespace lbm

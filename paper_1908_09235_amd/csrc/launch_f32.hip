@@ -25,11 +25,11 @@ void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks)
     }
 }
 void launch_init_f32(const Ctx& c, const double* rw, const double* r0, const double* u0,
-                     const double* v0, void* buf) {
+                     const double* v0, void* buf, void* other) {
     switch (c.storage) {
-    case 2: case 3: init_any<float, float>(c, rw, r0, u0, v0, buf); break;
-    case 4: case 5: init_any<_Float16, float>(c, rw, r0, u0, v0, buf); break;
-    default: init_any<float, double>(c, rw, r0, u0, v0, buf);
+    case 2: case 3: init_any<float, float>(c, rw, r0, u0, v0, buf, other); break;
+    case 4: case 5: init_any<_Float16, float>(c, rw, r0, u0, v0, buf, other); break;
+    default: init_any<float, double>(c, rw, r0, u0, v0, buf, other);
     }
 }
 
@@ -42,13 +42,13 @@ void launch_batch_f32(const BatchLaunch& L) {
     default: batch_any<float, double, 0>(L);
     }
 }
-int batch_occupancy_f32(int eos, int storage, int tile_w) {
+int batch_occupancy_f32(int eos, int storage, int tile_w, bool save_f) {
     switch (storage) {
-    case 2: return occupancy_any<float, float, 0>(eos, tile_w);
-    case 3: return occupancy_any<float, float, 1>(eos, tile_w);
-    case 4: return occupancy_any<_Float16, float, 1>(eos, tile_w);
-    case 5: return occupancy_any<_Float16, float, 2>(eos, tile_w);
-    default: return occupancy_any<float, double, 0>(eos, tile_w);
+    case 2: return occupancy_any<float, float, 0>(eos, tile_w, save_f);
+    case 3: return occupancy_any<float, float, 1>(eos, tile_w, save_f);
+    case 4: return occupancy_any<_Float16, float, 1>(eos, tile_w, save_f);
+    case 5: return occupancy_any<_Float16, float, 2>(eos, tile_w, save_f);
+    default: return occupancy_any<float, double, 0>(eos, tile_w, save_f);
     }
 }
 

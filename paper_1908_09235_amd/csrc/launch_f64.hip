@@ -11,8 +11,8 @@ void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks)
     boundary_any<double>(c, cur, b, nblocks);
 }
 void launch_init_f64(const Ctx& c, const double* rw, const double* r0, const double* u0,
-                     const double* v0, void* buf) {
-    init_any<double, double>(c, rw, r0, u0, v0, buf);
+                     const double* v0, void* buf, void* other) {
+    init_any<double, double>(c, rw, r0, u0, v0, buf, other);
 }
 void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
                    long long* unstable) {
@@ -24,8 +24,8 @@ void launch_batch_f64(const BatchLaunch& L) { batch_any<double, double, 0>(L); }
 void launch_batch_reduce(const BatchLaunch& L) {
     hipLaunchKernelGGL(k_reduce_batch<0>, dim3(L.red_grid), dim3(256), 0, L.stream, L.args);
 }
-int batch_occupancy_f64(int eos, int, int tile_w) {
-    return occupancy_any<double, double, 0>(eos, tile_w);
+int batch_occupancy_f64(int eos, int, int tile_w, bool save_f) {
+    return occupancy_any<double, double, 0>(eos, tile_w, save_f);
 }
 
 }  // namespace lbm

@@ -10,14 +10,14 @@ Phys<R> convert(const Phys<double>& d) {
     return phys_as<R>(d);
 }
 
-template <typename S, typename R, int EOS, bool MOM, int DEV>
+template <typename S, typename R, int EOS, bool MOM, int DEV, bool SAVEF>
 void main_t(const Ctx& c, const S* src, S* dst) {
     MainArgs<S> a{};
     a.src = src;
     a.dst = dst;
     a.flags = c.flags;
-    a.psiw = c.psiw;
     a.side_idx = c.side_idx;
+    a.psiw = c.psiw;
     a.side_mom = c.side_mom;
     a.side_f = c.side_f;
     a.partial = c.partial;
@@ -29,23 +29,26 @@ void main_t(const Ctx& c, const S* src, S* dst) {
     a.tile_h = c.tile_h;
     a.nsegs = c.nsegs;
     a.nstrips = c.nstrips;
-    hipLaunchKernelGGL((k_main<S, R, EOS, MOM, DEV>), dim3(c.nblocks), dim3(c.tile_w), 0,
+    a.side_mom_bytes = c.side_mom_bytes;
+    a.side_f_bytes = c.side_f_bytes;
+    hipLaunchKernelGGL((k_main<S, R, EOS, MOM, DEV, SAVEF>), dim3(c.nblocks), dim3(c.tile_w), 0,
                        c.stream, a, convert<R>(c.ph));
 }
 
-template <typename S, typename R, bool MOM, int DEV>
-void main_s(const Ctx& c, const void* src, void* dst) {
-    const S* s = static_cast<const S*>(src);
-    S* t = static_cast<S*>(dst);
-    if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, MOM, DEV>(c, s, t);
-    else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, MOM, DEV>(c, s, t);
-    else main_t<S, R, EOS_CS, MOM, DEV>(c, s, t);
+template <typename S, typename R, bool MOM, int DEV, bool SAVEF>
+void main_e(const Ctx& c, const S* s, S* t) {
+    if (c.eos == EOS_NONE) main_t<S, R, EOS_NONE, MOM, DEV, SAVEF>(c, s, t);
+    else if (c.eos == EOS_EXP) main_t<S, R, EOS_EXP, MOM, DEV, SAVEF>(c, s, t);
+    else main_t<S, R, EOS_CS, MOM, DEV, SAVEF>(c, s, t);
 }
 
 template <typename S, typename R, int DEV = 0>
 void main_any(const Ctx& c, const void* src, void* dst, bool moments) {
-    if (moments) main_s<S, R, true, DEV>(c, src, dst);
-    else main_s<S, R, false, DEV>(c, src, dst);
+    const S* s = static_cast<const S*>(src);
+    S* t = static_cast<S*>(dst);
+    if (moments) main_e<S, R, true, DEV, false>(c, s, t);
+    else if (c.save_f) main_e<S, R, false, DEV, true>(c, s, t);
+    else main_e<S, R, false, DEV, false>(c, s, t);
 }
 
 template <typename S, int DEV = 0>
@@ -56,52 +59,65 @@ void boundary_any(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
 
 template <typename S, typename R>
 void init_any(const Ctx& c, const double* rw, const double* r0, const double* u0,
-              const double* v0, void* buf) {
+              const double* v0, void* buf, void* other) {
     const dim3 g((c.nx + 255) / 256, c.ny);
     const Phys<R> ph = convert<R>(c.ph);
-    R* psiw = static_cast<R*>(c.psiw);
+    S* b0 = static_cast<S*>(buf);
+    S* b1 = static_cast<S*>(other);
     if (c.eos == EOS_EXP)
-        hipLaunchKernelGGL((k_psi_wall<R, EOS_EXP>), g, dim3(256), 0, c.stream, psiw, rw,
+        hipLaunchKernelGGL((k_psi_wall<S, R, EOS_EXP>), g, dim3(256), 0, c.stream, b0, b1, c.psiw, rw,
                            c.flags, c.nx, c.ny, c.pitch, ph);
     else if (c.eos == EOS_CS)
-        hipLaunchKernelGGL((k_psi_wall<R, EOS_CS>), g, dim3(256), 0, c.stream, psiw, rw,
+        hipLaunchKernelGGL((k_psi_wall<S, R, EOS_CS>), g, dim3(256), 0, c.stream, b0, b1, c.psiw, rw,
                            c.flags, c.nx, c.ny, c.pitch, ph);
     else
-        hipLaunchKernelGGL((k_psi_wall<R, EOS_NONE>), g, dim3(256), 0, c.stream, psiw, rw,
+        hipLaunchKernelGGL((k_psi_wall<S, R, EOS_NONE>), g, dim3(256), 0, c.stream, b0, b1, c.psiw, rw,
                            c.flags, c.nx, c.ny, c.pitch, ph);
-    hipLaunchKernelGGL(k_init_scatter<S>, g, dim3(256), 0, c.stream, static_cast<S*>(buf),
-                       c.flags, r0, u0, v0, c.nx, c.ny, c.pitch, c.plane, c.ph.rref, c.ref);
+    hipLaunchKernelGGL(k_init_scatter<S>, g, dim3(256), 0, c.stream, b0, c.flags, r0, u0, v0,
+                       c.nx, c.ny, c.pitch, c.plane, c.ph.rref, c.ref);
+}
+
+template <typename S, typename R, int DEV, bool SAVEF>
+void batch_main(const BatchLaunch& L) {
+    if (L.eos == EOS_EXP)
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_EXP, DEV, SAVEF>), dim3(L.main_grid),
+                           dim3(L.tile_w), 0, L.stream, L.args);
+    else if (L.eos == EOS_CS)
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_CS, DEV, SAVEF>), dim3(L.main_grid),
+                           dim3(L.tile_w), 0, L.stream, L.args);
+    else
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_NONE, DEV, SAVEF>), dim3(L.main_grid),
+                           dim3(L.tile_w), 0, L.stream, L.args);
 }
 
 template <typename S, typename R, int DEV>
 void batch_any(const BatchLaunch& L) {
     hipLaunchKernelGGL((k_boundary_batch<S, DEV>), dim3(L.bnd_grid), dim3(256), 0, L.stream,
                        L.args);
-    if (L.eos == EOS_EXP)
-        hipLaunchKernelGGL((k_main_batch<S, R, EOS_EXP, DEV>), dim3(L.main_grid),
-                           dim3(L.tile_w), 0, L.stream, L.args);
-    else if (L.eos == EOS_CS)
-        hipLaunchKernelGGL((k_main_batch<S, R, EOS_CS, DEV>), dim3(L.main_grid),
-                           dim3(L.tile_w), 0, L.stream, L.args);
-    else
-        hipLaunchKernelGGL((k_main_batch<S, R, EOS_NONE, DEV>), dim3(L.main_grid),
-                           dim3(L.tile_w), 0, L.stream, L.args);
+    if (L.save_f) batch_main<S, R, DEV, true>(L);
+    else batch_main<S, R, DEV, false>(L);
 }
 
-template <typename S, typename R, int DEV>
-int occupancy_any(int eos, int tile_w) {
+template <typename S, typename R, int DEV, bool SAVEF>
+int occupancy_e(int eos, int tile_w) {
     int n = 0;
     hipError_t e;
     if (eos == EOS_EXP)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_EXP, DEV>), tile_w, 0);
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_EXP, DEV, SAVEF>), tile_w, 0);
     else if (eos == EOS_CS)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_CS, DEV>), tile_w, 0);
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_CS, DEV, SAVEF>), tile_w, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_NONE, DEV>), tile_w, 0);
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_NONE, DEV, SAVEF>), tile_w, 0);
     return e == hipSuccess ? n : 0;
+}
+
+template <typename S, typename R, int DEV>
+int occupancy_any(int eos, int tile_w, bool save_f) {
+    return save_f ? occupancy_e<S, R, DEV, true>(eos, tile_w)
+                  : occupancy_e<S, R, DEV, false>(eos, tile_w);
 }
 
 }  // namespace lbm

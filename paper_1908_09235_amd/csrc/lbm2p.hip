@@ -71,20 +71,20 @@ void free_domain(lbm_domain* d) {
 
 inline int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
-// The workgroup width with the largest share of lanes that update a node
-// (the wider one within 1 %).
+// The widest workgroup whose share of lanes that update a node is within
+// 10 % of the best width's (wider strips re-read fewer halo columns and
+// measure faster at equal share).
 int default_tile_w(int nx) {
-    int best = 64;
-    double be = 0.0;
-    for (int w : {256, 128, 64}) {
-        const int ns = (nx + strip_cols(w) - 1) / strip_cols(w);
-        const double eff = (double)nx / ((double)ns * w);
-        if (eff > be + 0.01) {
-            be = eff;
-            best = w;
-        }
+    double eff[3], best = 0.0;
+    const int ws[3] = {256, 128, 64};
+    for (int k = 0; k < 3; ++k) {
+        const int ns = (nx + strip_cols(ws[k]) - 1) / strip_cols(ws[k]);
+        eff[k] = (double)nx / ((double)ns * ws[k]);
+        best = std::max(best, eff[k]);
     }
-    return best;
+    for (int k = 0; k < 3; ++k)
+        if (eff[k] >= 0.9 * best) return ws[k];
+    return 64;
 }
 
 inline long long storage_bytes(int storage) {
@@ -131,10 +131,13 @@ Ctx ctx(lbm_domain* d) {
     c.nstrips = d->nstrips;
     c.nblocks = d->nblocks;
     c.flags = d->flags;
-    c.psiw = d->psiw;
     c.side_idx = d->side_idx;
+    c.psiw = d->psiw;
     c.side_mom = d->side_mom;
     c.side_f = d->side_f;
+    c.side_mom_bytes = (unsigned)(3 * std::max(d->nslots, 1) * 8);
+    c.side_f_bytes = (unsigned)(9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8);
+    c.save_f = d->save_f;
     c.partial = d->partial;
     c.mom_out = d->mom_out;
     c.ref = nullptr;
@@ -289,7 +292,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         const long long pitch = (nx + 63) / 64 * 64;
         const long long esz = storage_bytes(s->storage);
         const long long extra = s->storage == LBM_STORE_F16NODE ? 4 * (pitch * ny + 256) : 0;
-        if (9 * (pitch * ny + 256) * esz + extra >= (1LL << 32)) return LBM_EINVAL;
+        // (below the out-of-range lane offset of the kernels)
+        if (9 * (pitch * ny + 256) * esz + extra >= (1LL << 32) - 256) return LBM_EINVAL;
     }
     const long long N = (long long)nx * ny;
     auto solid = [&](long long i) { return s->solid[i] != 0; };
@@ -380,7 +384,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->rule = s->rule;
     d->fix = s->fix;
     d->tile_w = s->tile_w ? s->tile_w : default_tile_w(nx);
-    d->tile_h = s->tile_h ? s->tile_h : 8;
+    d->tile_h = s->tile_h ? s->tile_h : 9;  // rows come in rotations of three
     d->nstrips = (nx + strip_cols(d->tile_w) - 1) / strip_cols(d->tile_w);
     d->nsegs = (ny + d->tile_h - 1) / d->tile_h;
     d->nblocks = d->nstrips * d->nsegs;
@@ -560,7 +564,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (hipMemsetAsync(d->f[1], 0, fbytes, d->stream) != hipSuccess) return LBM_EDEVICE;
     if ((rc = upload(d, &d->flags, flags))) return rc;
     if ((rc = upload(d, &d->side_idx, side_idx))) return rc;
-    if ((rc = dev_alloc(d, &d->psiw, (size_t)P * ny * 8))) return rc;
+    if (d->esize == 2 && (rc = dev_alloc(d, (void**)&d->psiw, (size_t)P * ny * 4))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->side_mom, (size_t)3 * std::max(nslots, 1) * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->side_f,
                         (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8)))
@@ -603,7 +607,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &dr0, r0))) return rc;
     if ((rc = upload(d, &du0, u0))) return rc;
     if ((rc = upload(d, &dv0, v0))) return rc;
-    if (d->storage == LBM_STORE_F64) launch_init_f64(ctx(d), drw, dr0, du0, dv0, d->f[1]);
+    if (d->storage == LBM_STORE_F64) launch_init_f64(ctx(d), drw, dr0, du0, dv0, d->f[1], d->f[0]);
     else {
         Ctx c = ctx(d);
         if (!rplane.empty()) {
@@ -615,7 +619,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
                     return LBM_EDEVICE;
             c.ref = reinterpret_cast<const float*>(static_cast<char*>(d->f[1]) + off);
         }
-        launch_init_f32(c, drw, dr0, du0, dv0, d->f[1]);
+        launch_init_f32(c, drw, dr0, du0, dv0, d->f[1], d->f[0]);
     }
     launch_main(d, d->f[1], d->f[0], false);
     d->cur = 0;
