@@ -297,3 +297,25 @@ def request_stream(rate: float, duration: float, pool: int = 128, seed: int = 5,
             return out
         key = "big" if rs.uniform() < big_fraction else rs.integers(0, pool - 1)
         out.append((t, key, rs.integers(steps_lo, steps_hi)))
+
+
+def cylinder_flow(re: float, fix: str = "A", d: float = 40.0, u0: float = 0.1,
+                  nx_d: float = 40.0, ny_d: float = 25.0, rule: str = "mls"):
+    """Steady flow past a circular cylinder (Sec. 4.1): domain nx_d D by
+    ny_d D, cylinder of diameter D centred at (15 D, 12.5 D) in units of
+    the paper's domain, uniform inlet velocity u0 at x = 0, fully developed
+    outlet, periodic in y; Re = u0 D / nu; single phase, BGK."""
+    nx, ny = int(round(nx_d * d)), int(round(ny_d * d))
+    nu = u0 * d / re
+    tau = 3.0 * nu + 0.5
+    cx, cy = 15.0 / 40.0 * nx_d * d, 0.5 * ny_d * d
+    shapes = [geo.Circle(cx, cy, 0.5 * d)]
+    rho0 = np.ones((ny, nx))
+    solid, owner, links = geo.build(nx, ny, shapes)
+    fl = ~solid.astype(bool)
+    p = Problem(nx=nx, ny=ny, solid=solid, links=links, rho0=rho0,
+                rho_wall=np.ones((ny, nx)), eos="none", tau=tau, mrt_s=mrt_rates(tau),
+                rule=rule, fix=fix, ux0=np.where(fl, u0, 0.0), uy0=np.zeros((ny, nx)),
+                open_x=True, inlet_u=u0, name=f"cylinder_re{re:g}_d{d:g}")
+    p.meta.update(owner=owner, cx=cx, cy=cy, d=d, u0=u0, re=re)
+    return p

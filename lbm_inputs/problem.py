@@ -20,7 +20,9 @@ COLLISIONS = ("bgk", "mrt")
 
 @dataclass
 class Problem:
-    """A doubly periodic D2Q9 domain with solid obstacles.
+    """A D2Q9 domain with solid obstacles, periodic in y and, unless
+    ``open_x`` is set (velocity inlet at x = 0, outflow at x = nx - 1),
+    in x.
 
     Arrays are indexed [y, x].  ``rho_wall`` is the constant virtual wall
     density of the contact-angle treatment; it is read at solid nodes only.
@@ -45,6 +47,8 @@ class Problem:
     uy0: Optional[np.ndarray] = None
     name: str = ""
     meta: dict = field(default_factory=dict)
+    open_x: bool = False         # velocity inlet at x = 0, outlet at nx - 1
+    inlet_u: float = 0.0         # inlet velocity (x component)
 
     def __post_init__(self):
         assert self.rule in RULES, self.rule

@@ -30,7 +30,8 @@ class _Desc(C.Structure):
                 ("gx", C.c_double), ("gy", C.c_double),
                 ("collision", C.c_int32), ("tau", C.c_double),
                 ("mrt_s", C.c_double * 9), ("rule", C.c_int32),
-                ("fix", C.c_int32), ("rho0", _D), ("ux0", _D), ("uy0", _D)]
+                ("fix", C.c_int32), ("rho0", _D), ("ux0", _D), ("uy0", _D),
+                ("open_x", C.c_int32), ("inlet_u", C.c_double)]
 
 
 _lib = None
@@ -55,6 +56,7 @@ def lib():
         L.ora_last_leaks.argtypes = [C.c_void_p, _D, C.c_int64]
         L.ora_last_leaks.restype = C.c_int64
         L.ora_counters.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.ora_wall_force.argtypes = [C.c_void_p, _D]
         L.ora_feq.argtypes = [C.c_double] * 3 + [_D]
         L.ora_guo.argtypes = [C.c_double] * 5 + [_D]
         L.ora_mrt_matrix.argtypes = [_D, _D]
@@ -123,6 +125,8 @@ class Oracle:
         d.rho0 = _dp(keep["rho0"])
         d.ux0 = _dp(keep["ux0"])
         d.uy0 = _dp(keep["uy0"])
+        d.open_x = 1 if getattr(p, "open_x", False) else 0
+        d.inlet_u = float(getattr(p, "inlet_u", 0.0))
         h = C.c_void_p()
         rc = L.ora_create(C.byref(d), C.byref(h))
         if rc != 0:
@@ -135,6 +139,12 @@ class Oracle:
         if h is not None and h.value:
             self._L.ora_destroy(h)
             self._h = None
+
+    def wall_force(self):
+        """Force on the walls during the last step (momentum exchange)."""
+        out = np.zeros(2)
+        self._L.ora_wall_force(self._h, _dp(out))
+        return out
 
     def step(self, n: int) -> np.ndarray:
         hist = np.zeros(max(n, 1))

@@ -13,8 +13,11 @@
  *   5. collision, Eq. (2), with the equilibrium of Eq. (4) and the forcing
  *      term of Guo et al. (2002), which the paper cites (Sec. 3.2); or the
  *      D2Q9 multiple-relaxation-time form of the same step
- *   6. streaming, Eq. (3)
- *   7. one curved-wall rule per cut link, Eqs. (7)-(14)
+ *   6. streaming, Eq. (3); with open x boundaries, the populations that
+ *      enter from outside: Zou-He velocity inlet at x = 0, fully developed
+ *      (zero-gradient) outlet at x = nx - 1 (Sec. 4.1)
+ *   7. one curved-wall rule per cut link, Eqs. (7)-(14), and the force on
+ *      the walls by momentum exchange (Sec. 4.1)
  *   8. per boundary node: the leak of Eq. (15) and the corrections of
  *      scheme A (Eq. 18), scheme B (Eqs. 20-22) or Bao et al. (Eq. 23)
  *   9. total mass, compensated (Neumaier) summation
@@ -280,6 +283,9 @@ struct ora_sim {
     double *leaks;
     int64_t counters[5];
     int64_t t;
+    int32_t open_x;
+    double inlet_u;
+    double force[2];
 };
 
 static void free_sim(ora_sim *s) {
@@ -319,6 +325,16 @@ int ora_create(const ora_desc *d, ora_sim **out) {
         if (fabs(d->mrt_s[7] - 1.0 / d->tau) > 1e-12 ||
             fabs(d->mrt_s[8] - 1.0 / d->tau) > 1e-12)
             return -1;
+    }
+    if (d->open_x != 0 && d->open_x != 1) return -1;
+    if (d->open_x) {
+        /* single phase only; the inlet density formula needs |U| < 1; the
+         * three outermost columns on each side are fluid, so that no wall
+         * rule reaches across the seam (x_ff of a cut link stays inside) */
+        if (d->eos != ORA_EOS_NONE || !(fabs(d->inlet_u) < 1.0) || d->nx < 8) return -1;
+        for (int y = 0; y < d->ny; ++y)
+            for (int x = 0; x < d->nx; ++x)
+                if ((x < 3 || x >= d->nx - 3) && d->solid[(int64_t)y * d->nx + x]) return -1;
     }
     const int nx = d->nx, ny = d->ny;
     const int64_t N = (int64_t)nx * ny;
@@ -461,6 +477,8 @@ int ora_create(const ora_desc *d, ora_sim **out) {
         for (int a = 0; a < 9; ++a) s->f[a * N + i] = feq[a];
     }
     s->t = 0;
+    s->open_x = d->open_x;
+    s->inlet_u = d->inlet_u;
     *out = s;
     return 0;
 }
@@ -547,7 +565,32 @@ static int one_step(ora_sim *s, double *mass_out) {
                 s->fn[a * N + i] = s->solid[j] ? NAN : s->fs[a * N + j];
             }
         }
+    /* 6b. open x boundaries (Sec. 4.1) */
+    if (s->open_x) {
+        const double U = s->inlet_u;
+        for (int y = 0; y < ny; ++y) {
+            /* inlet, x = 0: Zou and He (1997) for u = (U, 0); f1, f5, f8
+             * arrive from outside */
+            int64_t i = (int64_t)y * nx;
+            double *f = s->fn;
+            double rho = (f[0 * N + i] + f[2 * N + i] + f[4 * N + i] +
+                          2.0 * (f[3 * N + i] + f[6 * N + i] + f[7 * N + i])) /
+                         (1.0 - U);
+            f[1 * N + i] = f[3 * N + i] + 2.0 / 3.0 * rho * U;
+            f[5 * N + i] = f[7 * N + i] - 0.5 * (f[2 * N + i] - f[4 * N + i]) +
+                           1.0 / 6.0 * rho * U;
+            f[8 * N + i] = f[6 * N + i] + 0.5 * (f[2 * N + i] - f[4 * N + i]) +
+                           1.0 / 6.0 * rho * U;
+            /* outlet, x = nx - 1: f3, f6, f7 arrive from outside; fully
+             * developed flow copies them from x = nx - 2 */
+            int64_t o = (int64_t)y * nx + nx - 1;
+            f[3 * N + o] = f[3 * N + o - 1];
+            f[6 * N + o] = f[6 * N + o - 1];
+            f[7 * N + o] = f[7 * N + o - 1];
+        }
+    }
     /* 7-8. cut links, leak and correction, node by node */
+    s->force[0] = s->force[1] = 0.0;
     for (int64_t bi = 0; bi < s->nb; ++bi) {
         int64_t b = s->bnode[bi];
         int bx = (int)(b % nx), by = (int)(b / nx);
@@ -625,6 +668,9 @@ static int one_step(ora_sim *s, double *mass_out) {
             out_sum += in[m][0];
             in_sum += inc[m] + wall[m];
             s->fn[OPP[dirs[m]] * N + b] = inc[m];
+            /* momentum handed to the wall by this link */
+            s->force[0] += EX[dirs[m]] * (in[m][0] + inc[m]);
+            s->force[1] += EY[dirs[m]] * (in[m][0] + inc[m]);
         }
         double f0_before = s->fn[b];
         if (s->fix == ORA_FIX_A) {
@@ -693,6 +739,11 @@ int64_t ora_last_leaks(const ora_sim *s, double *out, int64_t cap) {
     int64_t n = s->nb < cap ? s->nb : cap;
     for (int64_t i = 0; i < n; ++i) out[i] = s->leaks[i];
     return s->nb;
+}
+
+void ora_wall_force(const ora_sim *s, double out[2]) {
+    out[0] = s->force[0];
+    out[1] = s->force[1];
 }
 
 void ora_counters(const ora_sim *s, int64_t out[5]) {

@@ -15,7 +15,10 @@
  *
  * Directions (D2Q9): 0 rest; 1 (+1,0); 2 (0,+1); 3 (-1,0); 4 (0,-1);
  * 5 (+1,+1); 6 (-1,+1); 7 (-1,-1); 8 (+1,-1).  Node index = y*nx + x.
- * The domain is periodic in x and y; walls are solid nodes.
+ * The domain is periodic in y, and in x unless open_x is set (flow past a
+ * cylinder, Sec. 4.1: a uniform velocity inlet at x = 0 by the scheme of
+ * Zou and He (1997) and a fully developed outlet at x = nx - 1); walls are
+ * solid nodes.
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -51,6 +54,8 @@ typedef struct {
     int32_t rule, fix;
     const double *rho0;            /* initial density per node               */
     const double *ux0, *uy0;       /* initial velocity (nullable = 0)        */
+    int32_t open_x;                /* 1: inlet at x = 0, outlet at nx - 1   */
+    double inlet_u;                /* inlet velocity (x component; y = 0)    */
 } ora_desc;
 
 typedef struct ora_sim ora_sim;
@@ -69,6 +74,9 @@ void ora_set_f(ora_sim *s, const double *f);
 /* Per-boundary-node mass leak of the last step (Eq. 15) after the fix,
  * in the order of ascending node index; returns the number of nodes. */
 int64_t ora_last_leaks(const ora_sim *s, double *out, int64_t cap);
+/* Force exerted on the walls during the last step by momentum exchange
+ * over the cut links: sum of e_a (f*_a(x_b, t) + f_abar(x_b, t+1)). */
+void ora_wall_force(const ora_sim *s, double out[2]);
 /* counters: [0] MLS u_f fallbacks, [1] IBB-L branch fallbacks,
  * [2] IBB-Q -> IBB-L fallbacks, [3] scheme-B degenerate nodes,
  * [4] scheme-A nodes with negative rest population. */
