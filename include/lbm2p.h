@@ -21,7 +21,9 @@
  *   Lattice: D2Q9, directions 0 rest, 1 (+1,0), 2 (0,+1), 3 (-1,0),
  *   4 (0,-1), 5 (+1,+1), 6 (-1,+1), 7 (-1,-1), 8 (+1,-1).
  *   Host arrays of nodes are row-major with index y*nx + x.
- *   The domain is periodic in x and y; walls are solid nodes.  A cut link
+ *   The domain is periodic in y, and in x unless open_x is set (Sec. 4.2:
+ *   a uniform velocity inlet at x = 0 by the scheme of Zou and He (1997),
+ *   a fully developed outlet at x = nx - 1); walls are solid nodes.  A cut link
  *   (x, y, dir) joins a fluid node to a solid node at (x, y) + e_dir; every
  *   such adjacency must be listed exactly once.
  *
@@ -137,7 +139,10 @@ typedef struct {
     int32_t rule;              /* enum lbm_rule                             */
     int32_t fix;               /* enum lbm_fix; B and BAO need FH or MLS    */
     int32_t storage;           /* enum lbm_storage                          */
-    int32_t reserved;          /* must be 0                                 */
+    int32_t open_x;            /* 0 periodic in x; 1 velocity inlet at x = 0
+                                  and outlet at x = nx - 1 (single phase
+                                  only; nx >= 8; columns 0..2 and
+                                  nx-3..nx-1 fluid)                        */
     const double *rho0;        /* host, nx*ny initial density (> 0 on fluid)*/
     const double *ux0, *uy0;   /* host, nx*ny initial velocity, or NULL     */
     int64_t history_capacity;  /* mass-history ring entries; 0 = 1048576   */
@@ -148,6 +153,8 @@ typedef struct {
     double rho_ref;            /* reference density of the deviation forms
                                   (>= 0; 0 = mean of rho0 over fluid nodes);
                                   ignored by the other forms              */
+    double inlet_u;            /* open_x: inlet velocity, x component
+                                  (|inlet_u| < 1; the y component is 0)    */
 } lbm_desc;
 
 typedef struct lbm_domain lbm_domain;
@@ -205,6 +212,12 @@ int lbm_set_profiling(lbm_domain *d, int every);
 int lbm_kernel_times(lbm_domain *d, double *main_ms, int64_t *main_count,
                      double *boundary_ms, int64_t *boundary_count);
 
+/* Force exerted on the walls during the last step, by momentum exchange
+ * over the cut links (Sec. 4.2): out = sum of e_a (f*_a(x_b, t) +
+ * f_abar(x_b, t + 1)), summed in a fixed order.  Zero before the first
+ * step. */
+int lbm_wall_force(lbm_domain *d, double out[2]);
+
 /* Facts about the built domain: [0] fluid nodes, [1] cut links,
  * [2] boundary nodes, [3] bytes of device memory held, [4] tile_w,
  * [5] tile_h, [6] main-kernel workgroups, [7] boundary-rule fallbacks
@@ -247,7 +260,8 @@ typedef struct {
 int lbm_batch_create(const lbm_batch_desc *bd, lbm_batch **out);
 
 /* Build an instance from a descriptor (as lbm_create_domain: same
- * validation and errors; desc->stream, tile_w and tile_h are ignored) that
+ * validation and errors, and open_x must be 0; desc->stream, tile_w and
+ * tile_h are ignored) that
  * will run `steps` steps and then stop.  *slot receives its slot index.
  * LBM_ENOMEM when no slot is free or the arena has no room for it; the
  * batch is unchanged then.  The instance joins the next lbm_batch_run. */

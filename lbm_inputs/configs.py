@@ -301,7 +301,7 @@ def request_stream(rate: float, duration: float, pool: int = 128, seed: int = 5,
 
 def cylinder_flow(re: float, fix: str = "A", d: float = 40.0, u0: float = 0.1,
                   nx_d: float = 40.0, ny_d: float = 25.0, rule: str = "mls"):
-    """Steady flow past a circular cylinder (Sec. 4.1): domain nx_d D by
+    """Steady flow past a circular cylinder (Sec. 4.2): domain nx_d D by
     ny_d D, cylinder of diameter D centred at (15 D, 12.5 D) in units of
     the paper's domain, uniform inlet velocity u0 at x = 0, fully developed
     outlet, periodic in y; Re = u0 D / nu; single phase, BGK."""

@@ -15,9 +15,9 @@
  *      D2Q9 multiple-relaxation-time form of the same step
  *   6. streaming, Eq. (3); with open x boundaries, the populations that
  *      enter from outside: Zou-He velocity inlet at x = 0, fully developed
- *      (zero-gradient) outlet at x = nx - 1 (Sec. 4.1)
+ *      (zero-gradient) outlet at x = nx - 1 (Sec. 4.2)
  *   7. one curved-wall rule per cut link, Eqs. (7)-(14), and the force on
- *      the walls by momentum exchange (Sec. 4.1)
+ *      the walls by momentum exchange (Sec. 4.2)
  *   8. per boundary node: the leak of Eq. (15) and the corrections of
  *      scheme A (Eq. 18), scheme B (Eqs. 20-22) or Bao et al. (Eq. 23)
  *   9. total mass, compensated (Neumaier) summation
@@ -565,7 +565,7 @@ static int one_step(ora_sim *s, double *mass_out) {
                 s->fn[a * N + i] = s->solid[j] ? NAN : s->fs[a * N + j];
             }
         }
-    /* 6b. open x boundaries (Sec. 4.1) */
+    /* 6b. open x boundaries (Sec. 4.2) */
     if (s->open_x) {
         const double U = s->inlet_u;
         for (int y = 0; y < ny; ++y) {

@@ -16,7 +16,7 @@
  * Directions (D2Q9): 0 rest; 1 (+1,0); 2 (0,+1); 3 (-1,0); 4 (0,-1);
  * 5 (+1,+1); 6 (-1,+1); 7 (-1,-1); 8 (+1,-1).  Node index = y*nx + x.
  * The domain is periodic in y, and in x unless open_x is set (flow past a
- * cylinder, Sec. 4.1: a uniform velocity inlet at x = 0 by the scheme of
+ * cylinder, Sec. 4.2: a uniform velocity inlet at x = 0 by the scheme of
  * Zou and He (1997) and a fully developed outlet at x = nx - 1); walls are
  * solid nodes.
  */

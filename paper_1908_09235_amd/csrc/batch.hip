@@ -466,6 +466,7 @@ int lbm_batch_create(const lbm_batch_desc* bd, lbm_batch** out) {
 
 int lbm_batch_add(lbm_batch* b, const lbm_desc* d, int64_t steps, int32_t* slot) {
     if (!b || !d || !slot || steps < 0) return LBM_EINVAL;
+    if (d->open_x != 0) return LBM_EINVAL;  // batched instances are periodic
     int s = -1;
     int rc = batch_add(b, d, steps, &s);
     if (rc == LBM_OK) *slot = s;
@@ -610,6 +611,7 @@ int lbm_server_create(const lbm_batch_desc* bd, int64_t chunk_steps, lbm_server*
 int lbm_server_submit(lbm_server* s, const lbm_desc* d, int64_t steps, int64_t* id) {
     if (!s || !d || !id || steps < 1) return LBM_EINVAL;
     if (d->storage != s->b->bd.storage || d->eos != s->b->bd.eos) return LBM_EINVAL;
+    if (d->open_x != 0) return LBM_EINVAL;
     lbm_server::Req r{s->next_id++, *d, steps};
     s->queue.push_back(r);
     *id = r.id;

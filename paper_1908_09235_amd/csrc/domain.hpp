@@ -58,6 +58,10 @@ struct lbm_domain {
     long long* unstable = nullptr;
     double* mom_out = nullptr;
     int* lref = nullptr;   // per link: side slot whose density encodes its ghost
+    int open_x = 0;        // velocity inlet at x = 0, outlet at x = nx - 1
+    double inlet_u = 0.0;
+    double* force = nullptr;   // wall force partials, two per link block
+    bool force_valid = false;  // a boundary pass has written them
     int nb = 0, nl = 0;
     int nslot_links = 0;
     int *lnode = nullptr, *lmeta = nullptr, *lghost = nullptr, *lxf = nullptr,

@@ -11,6 +11,8 @@
 //     written into the solid neighbour's slot of the opposite direction
 //     (the "ghost" slot: the only slot a pull from the fluid node reads
 //     there).  Scheme A adds the leak to the node's own rest population.
+//     Each block also sums the momentum its links hand to the wall; with
+//     open x boundaries, further blocks set the inlet and outlet columns.
 //
 //   k_main(cur -> nxt): pull-streaming (Eq. 3) of all nine populations,
 //     density, pseudopotential, the force of Eq. (16), the velocity of
@@ -466,6 +468,15 @@ struct BndArgs {
     long long slot, t;
     long long* __restrict__ unstable;
     int do_reduce;
+    // force on the walls (Sec. 4.2, momentum exchange): two FP64 partials
+    // per link block (null: not formed)
+    double* __restrict__ force;
+    // open x boundaries (Sec. 4.2): blocks nlink_blocks .. of the grid take
+    // one row each lane
+    int nlink_blocks;
+    int open_x;
+    int nx, ny, pitch;
+    double inlet_u;
 };
 
 constexpr int LK_PAD = 15;
@@ -594,6 +605,68 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
         }
         A[node] = S(double(A[node]) + (out_sum - in_sum));
     }
+    if (b.force) {
+        // momentum handed to the wall by this link, e_a (f*_a + f_abar(t+1)),
+        // summed over the block by a fixed tree
+        __shared__ double s_fx[256], s_fy[256];
+        const double m = fab + r;
+        s_fx[tid] = active ? double(cx(d)) * m : 0.0;
+        s_fy[tid] = active ? double(cy(d)) * m : 0.0;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) {
+                s_fx[tid] += s_fx[tid + w];
+                s_fy[tid] += s_fy[tid + w];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            b.force[2 * blk] = s_fx[0];
+            b.force[2 * blk + 1] = s_fy[0];
+        }
+    }
+}
+
+// Open x boundaries (Sec. 4.2), lane y of block `blk` takes row y.  The
+// seam between columns nx-1 and 0 is cut: the populations a node there
+// pulls across it are written into the slots it pulls them from.
+//   inlet, x = 0: velocity (U, 0) by the scheme of Zou and He (1997); the
+//     node's density follows from the six populations that arrive from the
+//     interior, and f1, f5, f8 are set so that its moments give (U, 0).
+//   outlet, x = nx - 1: fully developed flow, f3, f6, f7 equal to those of
+//     the node at nx - 2.
+// No cut link reads or writes these slots (the three outermost columns on
+// each side are fluid), so the rows run beside the link blocks.
+template <typename S, int DEV>
+__device__ __forceinline__ void open_rows(S* __restrict__ A, const BndArgs& b, int blk) {
+    const int y = blk * 256 + int(threadIdx.x);
+    if (y >= b.ny) return;
+    const long long P = b.plane;
+    float* const rpl = reinterpret_cast<float*>(A + 9 * P);
+    auto ref = [&](int q, long long n) {
+        if constexpr (DEV == 2) return wt(q) * double(rpl[n]);
+        return DEV == 1 ? wt(q) * b.rref : 0.0;
+    };
+    auto ld = [&](int q, long long n) { return double(A[q * P + n]) + ref(q, n); };
+    auto st = [&](int q, long long n, double v) { A[q * P + n] = S(v - ref(q, n)); };
+    const long long p = b.pitch, e = b.nx - 1;
+    const long long r0 = y * p;
+    const long long rm = (y == 0 ? b.ny - 1 : y - 1) * p;
+    const long long rp = (y == b.ny - 1 ? 0 : y + 1) * p;
+    // populations of (0, y) after streaming, each where the pull reads it
+    const double f0 = ld(0, r0), f2 = ld(2, rm), f4 = ld(4, rp);
+    const double f3 = ld(3, r0 + 1), f6 = ld(6, rm + 1), f7 = ld(7, rp + 1);
+    const double U = b.inlet_u;
+    const double rho = (f0 + f2 + f4 + 2.0 * (f3 + f6 + f7)) / (1.0 - U);
+    const double h = 0.5 * (f2 - f4), s6 = 1.0 / 6.0 * rho * U;
+    st(1, r0 + e, f3 + 2.0 / 3.0 * rho * U);
+    st(5, rm + e, f7 - h + s6);
+    st(8, rp + e, f6 + h + s6);
+    // outlet: (nx-1, y) pulls f3, f6, f7 through (0, y), (0, y-1), (0, y+1);
+    // lane y fills row y of the three planes
+    st(3, r0, ld(3, r0 + e));
+    st(6, r0, ld(6, r0 + e));
+    st(7, r0, ld(7, r0 + e));
 }
 
 // The last block reduces the previous main pass's mass partials.
@@ -601,6 +674,10 @@ template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
     if (blockIdx.x == gridDim.x - 1) {
         if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
+        return;
+    }
+    if (int(blockIdx.x) >= b.nlink_blocks) {
+        open_rows<S, DEV>(A, b, blockIdx.x - b.nlink_blocks);
         return;
     }
     boundary_block<S, DEV>(A, b, blockIdx.x);
@@ -809,6 +886,11 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.t = 0;
         a.unstable = nullptr;
         a.do_reduce = 0;
+        a.force = nullptr;
+        a.nlink_blocks = 0;
+        a.open_x = 0;
+        a.nx = a.ny = a.pitch = 0;
+        a.inlet_u = 0.0;
         __syncthreads();  // the previous block is done with the LDS
         boundary_block<S, DEV>(static_cast<S*>(I.f[st.t & 1]), a, e.y);
     }

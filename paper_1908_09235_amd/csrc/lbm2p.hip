@@ -151,6 +151,8 @@ void launch_main(lbm_domain* d, const void* src, void* dst, bool moments) {
     else launch_main_f32(ctx(d), src, dst, moments);
 }
 
+int link_blocks(const lbm_domain* d) { return (d->nslot_links + 255) / 256; }
+
 BndArgs bnd_args(lbm_domain* d) {
     BndArgs b{};
     b.nslot = d->nslot_links;
@@ -176,15 +178,24 @@ BndArgs bnd_args(lbm_domain* d) {
     b.do_reduce = d->pending ? 1 : 0;
     b.t = d->pending_t;
     b.slot = d->pending_t % d->cap;
+    b.force = d->force;
+    b.nlink_blocks = link_blocks(d);
+    b.open_x = d->open_x;
+    b.nx = d->nx;
+    b.ny = d->ny;
+    b.pitch = d->pitch;
+    b.inlet_u = d->inlet_u;
     return b;
 }
 
 void launch_boundary(lbm_domain* d, void* cur) {
     BndArgs b = bnd_args(d);
-    const int nbb = (d->nslot_links + 255) / 256 + 1;
+    // link blocks, then the open rows, then the block that reduces
+    const int nbb = b.nlink_blocks + (d->open_x ? (d->ny + 255) / 256 : 0) + 1;
     if (d->storage == LBM_STORE_F64) launch_boundary_f64(ctx(d), cur, b, nbb);
     else launch_boundary_f32(ctx(d), cur, b, nbb);
     d->pending = false;
+    d->force_valid = true;
 }
 
 void reduce_pending(lbm_domain* d) {
@@ -270,7 +281,17 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (s->eos < 0 || s->eos > 2 || s->collision < 0 || s->collision > 1) return LBM_EINVAL;
     if (s->storage < LBM_STORE_F64 || s->storage > LBM_STORE_F16NODE) return LBM_EINVAL;
     if (!(s->rho_ref >= 0.0) || !std::isfinite(s->rho_ref)) return LBM_EINVAL;
-    if (s->reserved != 0) return LBM_EINVAL;
+    if (s->open_x != 0 && s->open_x != 1) return LBM_EINVAL;
+    if (s->open_x) {
+        // single phase; the inlet density needs |U| < 1; no wall within
+        // three columns of the inlet or the outlet, so that no wall rule
+        // reads a slot the open rows write
+        if (s->eos != LBM_EOS_NONE || !(std::fabs(s->inlet_u) < 1.0) || nx < 8)
+            return LBM_EINVAL;
+        for (int y = 0; y < ny; ++y)
+            for (int x : {0, 1, 2, nx - 3, nx - 2, nx - 1})
+                if (s->solid[(long long)y * nx + x]) return LBM_EINVAL;
+    }
     if ((s->fix == LBM_FIX_B || s->fix == LBM_FIX_BAO) && s->rule != LBM_RULE_FH &&
         s->rule != LBM_RULE_MLS)
         return LBM_EINVAL;
@@ -383,6 +404,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->coll = s->collision;
     d->rule = s->rule;
     d->fix = s->fix;
+    d->open_x = s->open_x;
+    d->inlet_u = s->open_x ? s->inlet_u : 0.0;
     d->tile_w = s->tile_w ? s->tile_w : default_tile_w(nx);
     d->tile_h = s->tile_h ? s->tile_h : 9;  // rows come in rotations of three
     d->nstrips = (nx + strip_cols(d->tile_w) - 1) / strip_cols(d->tile_w);
@@ -587,6 +610,9 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &d->lc, lc))) return rc;
     if ((rc = upload(d, &d->luw, luw))) return rc;
     if (!lref.empty() && (rc = upload(d, &d->lref, lref))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->force,
+                        (size_t)2 * std::max(link_blocks(d), 1) * 8)))
+        return rc;
 
     const long long minus1 = -1;
     if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
@@ -800,6 +826,24 @@ int lbm_total_mass(lbm_domain* d, double* out) {
     return LBM_OK;
 }
 
+int lbm_wall_force(lbm_domain* d, double out[2]) {
+    if (!d || !out) return LBM_EINVAL;
+    out[0] = out[1] = 0.0;
+    if (!d->force_valid) return LBM_OK;
+    const int n = link_blocks(d);
+    std::vector<double> part((size_t)2 * std::max(n, 1), 0.0);
+    if (n > 0 && hipMemcpyAsync(part.data(), d->force, (size_t)2 * n * 8,
+                                hipMemcpyDeviceToHost, d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
+    // block partials in block order
+    for (int k = 0; k < n; ++k) {
+        out[0] += part[2 * k];
+        out[1] += part[2 * k + 1];
+    }
+    return LBM_OK;
+}
+
 int lbm_time(lbm_domain* d, int64_t* t) {
     if (!d || !t) return LBM_EINVAL;
     *t = d->t;
@@ -898,6 +942,7 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
     d->t = (long long)hdr[1];
     d->pending = false;
     d->pending_t = d->t;
+    d->force_valid = false;
     return LBM_OK;
 }
 

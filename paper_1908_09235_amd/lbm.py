@@ -44,13 +44,13 @@ class lbm_desc(C.Structure):
                 ("gravity", C.c_double * 2), ("tau", C.c_double),
                 ("mrt_s", C.c_double * 9), ("rule", C.c_int32),
                 ("fix", C.c_int32), ("storage", C.c_int32),
-                ("reserved", C.c_int32),
+                ("open_x", C.c_int32),
                 ("rho0", C.POINTER(C.c_double)),
                 ("ux0", C.POINTER(C.c_double)),
                 ("uy0", C.POINTER(C.c_double)),
                 ("history_capacity", C.c_int64), ("stream", C.c_void_p),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32),
-                ("rho_ref", C.c_double)]
+                ("rho_ref", C.c_double), ("inlet_u", C.c_double)]
 
 
 class lbm_batch_desc(C.Structure):
@@ -76,6 +76,7 @@ EXPORTS = {
     "lbm_moments_device": (C.c_int, [_H, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_total_mass": (C.c_int, [_H, _D]),
     "lbm_time": (C.c_int, [_H, C.POINTER(C.c_int64)]),
+    "lbm_wall_force": (C.c_int, [_H, _D]),
     "lbm_mass_history": (C.c_int, [_H, _D, C.c_int64, C.POINTER(C.c_int64)]),
     "lbm_unstable_step": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_get_state": (C.c_int, [_H, C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -179,7 +180,8 @@ def make_desc(problem, storage="f64", tile_w=0, tile_h=0, stream=None,
     d.rule = RULE[p.rule]
     d.fix = FIX[p.fix]
     d.storage = STORAGE[storage]
-    d.reserved = 0
+    d.open_x = 1 if getattr(p, "open_x", False) else 0
+    d.inlet_u = float(getattr(p, "inlet_u", 0.0))
     d.rho0 = _dptr(keep["rho0"])
     d.ux0 = _dptr(keep["ux0"])
     d.uy0 = _dptr(keep["uy0"])
@@ -285,6 +287,13 @@ def lbm_destroy(h):
     lib().lbm_destroy(h)
 
 
+def lbm_wall_force(h):
+    """Force on the walls during the last step (momentum exchange)."""
+    out = np.zeros(2)
+    _check(lib().lbm_wall_force(h, out.ctypes.data_as(_D)), "lbm_wall_force")
+    return out
+
+
 def lbm_status_string(code):
     return lib().lbm_status_string(code).decode()
 
@@ -304,6 +313,9 @@ class Domain:
 
     def total_mass(self):
         return lbm_total_mass(self.h)
+
+    def wall_force(self):
+        return lbm_wall_force(self.h)
 
     def mass_history(self, cap=None):
         return lbm_mass_history(self.h, cap if cap is not None else lbm_time(self.h) + 1)

@@ -1,0 +1,68 @@
+"""Observables of steady flow past a cylinder (Sec. 4.2, Table 1), read
+from the velocity field and the wall force.
+
+  wake length  2L/D, with L from the rearmost point of the cylinder to the
+               end of the recirculation on the wake axis (where u_x turns
+               from negative to positive, linear between nodes);
+  separation   theta_s, the angle from the rear stagnation point at which
+               the tangential velocity next to the wall changes sign.  It is
+               read on circles of radius R + delta (bilinear interpolation,
+               solid nodes at rest) and extrapolated linearly to delta = 0;
+  drag         C_d = F_x / (0.5 rho U0^2 D) with rho = 1.
+"""
+import numpy as np
+
+
+def drag_coefficient(fx, u0, d, rho=1.0):
+    return fx / (0.5 * rho * u0 * u0 * d)
+
+
+def wake_length(ux, cx, cy, r):
+    """2L/D from the row through the cylinder's centre (cy on a node row)."""
+    row = ux[int(round(cy))]
+    x0 = cx + r
+    i = int(np.floor(x0)) + 1
+    if row[i] >= 0:
+        return 0.0
+    while i < len(row) and row[i] < 0:
+        i += 1
+    if i == len(row):
+        return float("inf")
+    a, b = row[i - 1], row[i]
+    xr = (i - 1) + a / (a - b)
+    return 2.0 * (xr - x0) / (2.0 * r)
+
+
+def _bilinear(f, x, y):
+    x0 = np.floor(x).astype(int)
+    y0 = np.floor(y).astype(int)
+    tx, ty = x - x0, y - y0
+    return ((1 - tx) * (1 - ty) * f[y0, x0] + tx * (1 - ty) * f[y0, x0 + 1] +
+            (1 - tx) * ty * f[y0 + 1, x0] + tx * ty * f[y0 + 1, x0 + 1])
+
+
+def separation_angle(ux, uy, solid, cx, cy, r, deltas=(1.5, 2.5)):
+    """theta_s in degrees, upper and lower halves averaged."""
+    fl = ~solid.astype(bool)
+    u = np.where(fl, ux, 0.0)
+    v = np.where(fl, uy, 0.0)
+    phi = np.radians(np.linspace(1.0, 120.0, 23801))
+    out = []
+    for dl in deltas:
+        rr = r + dl
+        side = []
+        for sgn in (1.0, -1.0):
+            x = cx + rr * np.cos(phi)
+            y = cy + sgn * rr * np.sin(phi)
+            # the lower half is the mirror image: v changes sign
+            ut = -_bilinear(u, x, y) * np.sin(phi) + sgn * _bilinear(v, x, y) * np.cos(phi)
+            # reverse flow (u_t > 0) behind the separation point
+            k = int(np.argmax(ut < 0))
+            if k == 0:
+                side.append(0.0)
+                continue
+            t = ut[k - 1] / (ut[k - 1] - ut[k])
+            side.append(np.degrees(phi[k - 1] + t * (phi[k] - phi[k - 1])))
+        out.append(0.5 * (side[0] + side[1]))
+    (d1, d2), (a1, a2) = deltas, out
+    return a1 + (a1 - a2) * d1 / (d2 - d1)

@@ -40,6 +40,7 @@ def test_null_arguments_are_rejected(L):
     assert lib.lbm_step(None, 1) == L.LBM_EINVAL
     assert lib.lbm_total_mass(None, None) == L.LBM_EINVAL
     assert lib.lbm_moments(None, None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_wall_force(None, None) == L.LBM_EINVAL
     n = ctypes.c_size_t()
     assert lib.lbm_get_state(None, None, ctypes.byref(n)) == L.LBM_EINVAL
     lib.lbm_destroy(None)
@@ -84,11 +85,25 @@ def _bad_problem(bad):
         rw = p.rho_wall.copy()
         rw[:] = -1.0
         return p.with_(rho_wall=rw)
+    if bad == "open_eos":  # open boundaries are single phase only
+        return p.with_(open_x=True, inlet_u=0.05)
+    c = cfg.cylinder_flow(20.0, d=8.0, nx_d=6.0, ny_d=4.0)
+    if bad == "open_speed":
+        return c.with_(inlet_u=1.0)
+    if bad == "open_nan":
+        return c.with_(inlet_u=float("nan"))
+    if bad == "open_edge":  # a solid node two columns from the inlet
+        from lbm_inputs import geometry as geo
+        m = c.meta
+        solid, _, links = geo.build(c.nx, c.ny, [geo.Circle(m["cx"], m["cy"], 0.5 * m["d"]),
+                                                 geo.Circle(2.0, 5.0, 0.5)])
+        return c.with_(solid=solid, links=links)
     raise AssertionError(bad)
 
 
 BAD = ["q0", "q_gt_1", "missing", "dup", "fluid_target", "tau", "fh_pole",
-       "fixb_rule", "rho0", "cs_psi", "moving_ibb", "mrt_rates", "wall_density"]
+       "fixb_rule", "rho0", "cs_psi", "moving_ibb", "mrt_rates", "wall_density",
+       "open_eos", "open_speed", "open_nan", "open_edge"]
 
 
 @pytest.mark.parametrize("bad", BAD)
@@ -119,8 +134,9 @@ def test_bad_launch_shape_and_storage_are_rejected(L):
         assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
     d.rho_ref = 0.0
     d.storage = 0
-    d.reserved = 1
-    assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+    for ox in (-1, 2):
+        d.open_x = ox
+        assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
 
 
 def test_binding_struct_layout_matches_header(L, tmp_path):

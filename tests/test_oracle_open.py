@@ -1,4 +1,4 @@
-"""Pins of the oracle's flow-past-a-cylinder parts (Sec. 4.1): the Zou-He
+"""Pins of the oracle's flow-past-a-cylinder parts (Sec. 4.2): the Zou-He
 velocity inlet, the fully developed outlet and the momentum-exchange force
 on the walls.  Each is checked against a property fixed by the mathematics,
 not against its own formula: the inlet node's moments come out as the
