@@ -4,8 +4,7 @@
 Workload: the droplet resting on a cylinder above a floor, 2048 x 2048,
 Carnahan-Starling EOS at 0.86 Tc, MRT with s_nu = 1/tau, tau = 0.8, MLS with
 scheme B, synthetic seeded geometry (no dataset).  One step = one pass of the
-whole hot path: one launch whose tiles first do the boundary work of the
-nodes they pull, then the fused stream/force/collide rows.
+whole hot path (boundary pass + fused stream/force/collide pass).
 
 Prints one JSON line: MLUPS over fluid nodes (whole job) of the plain form
 with FP32 populations (FP64 arithmetic), the roofline of the main kernel
@@ -310,8 +309,10 @@ def main():
                     help="droplet geometry scale (16 = 2048 x 2048)")
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
-    ap.add_argument("--prof-every", type=int, default=1,
-                    help="time the kernels of every n-th step with HIP events")
+    ap.add_argument("--prof-every", type=int, default=50,
+                    help="time the kernels of every n-th step with HIP events "
+                         "(events between the launches of every step would "
+                         "add their own cost to the timed steps)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--precision-steps", type=int, default=2000,
                     help="steps of the 8192 x 4096 precision-form comparison (0: skip)")
@@ -411,7 +412,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_main", "kernel_ms": round(r["main_ms"], 5),
                      "kernel_samples": r["samples"],
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "boundary_kernel_ms": round(r["bnd_ms"], 5)},
         "cpu_baseline": cpu,
         "also": also,
         "precision": prec,

@@ -168,7 +168,7 @@ BInst make_inst(lbm_domain* d) {
     I.f[0] = d->f[0];
     I.f[1] = d->f[1];
     I.flags = d->flags;
-    I.side_mom_bytes = (unsigned)(4 * std::max(d->nslots, 1) * 8);
+    I.side_mom_bytes = (unsigned)(3 * std::max(d->nslots, 1) * 8);
     I.side_f_bytes = (unsigned)(9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8);
     I.side_idx = d->side_idx;
     I.psiw = d->psiw;

@@ -49,29 +49,18 @@ struct lbm_domain {
     uint8_t* flags = nullptr;
     float* psiw = nullptr;  // FP16 storage: psi_w of solid nodes in FP32
     int* side_idx = nullptr;
-    // side arrays and mass partials; a fused domain keeps two of each, the
-    // pass that produces f*(t) writing those of parity t & 1 (an instance
-    // of a batch keeps one: its boundary pass is a launch of its own)
     double* side_mom = nullptr;
     double* side_f = nullptr;
-    double* partial = nullptr;
-    double* side_mom2 = nullptr;
-    double* side_f2 = nullptr;
-    double* partial2 = nullptr;
     int nslots = 0;
     bool save_f = false;
-    bool fused = false;       // boundary work inside the main pass
-    int* tl_off = nullptr;    // per-tile link chunks (fused)
-    int* tl_link = nullptr;
-    size_t tl_off_bytes = 0, tl_link_bytes = 0;
-    std::vector<int> h_lnode, h_lmeta;  // host copies for rebuilding them
+    double* partial = nullptr;
     double* hist = nullptr;
     long long* unstable = nullptr;
     double* mom_out = nullptr;
     int* lref = nullptr;   // per link: side slot whose density encodes its ghost
     int open_x = 0;        // velocity inlet at x = 0, outlet at x = nx - 1
     double inlet_u = 0.0;
-    double* force = nullptr;   // wall force partials, two per tile
+    double* force = nullptr;   // wall force partials, two per link block
     bool force_valid = false;  // a boundary pass has written them
     int nb = 0, nl = 0;
     int nslot_links = 0;

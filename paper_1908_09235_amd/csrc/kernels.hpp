@@ -2,35 +2,29 @@
 //
 // State between steps: buffer `cur` holds the post-collision populations
 // f*(t) in structure-of-arrays layout, nine planes of ny rows of `pitch`
-// elements.  A step is one launch, k_main(cur -> nxt), in two phases per
-// tile:
+// elements.  A step is two launches:
 //
-//   boundary work (link_chunk): one lane per cut link whose boundary node
-//     the tile pulls evaluates the wall rule (Eqs. 7-14) from f*(t) and
-//     the node's moments saved by the previous pass; the first lane of
-//     each boundary node then forms the node's sums for scheme B or Bao and
-//     the leak of Eq. (15) for scheme A.  Each incoming population is
+//   k_boundary(cur): one lane per cut link evaluates the wall rule
+//     (Eqs. 7-14) from f*(t) and the node's saved moments; the first lane
+//     of each boundary node then forms the node's sums for scheme B or Bao
+//     and the leak of Eq. (15) for scheme A.  Each incoming population is
 //     written into the solid neighbour's slot of the opposite direction
 //     (the "ghost" slot: the only slot a pull from the fluid node reads
-//     there); scheme A adds the leak to the node's rest population.  The
-//     tile also sums the momentum its own links hand to the wall and, with
-//     open x boundaries, sets the inlet and outlet slots it pulls.
+//     there).  Scheme A adds the leak to the node's own rest population.
+//     Each block also sums the momentum its links hand to the wall; with
+//     open x boundaries, further blocks set the inlet and outlet columns.
 //
-//   rows: pull-streaming (Eq. 3) of all nine populations, density,
-//     pseudopotential, the force of Eq. (16), the velocity of Eq. (5) and
-//     collision (Eq. 2), fused.  A workgroup owns a strip of tile_w
-//     columns and marches through tile_h rows, keeping psi of three
+//   k_main(cur -> nxt): pull-streaming (Eq. 3) of all nine populations,
+//     density, pseudopotential, the force of Eq. (16), the velocity of
+//     Eq. (5) and collision (Eq. 2), fused.  A workgroup owns a strip of
+//     tile_w columns and marches through tile_h rows, keeping psi of three
 //     consecutive rows in a four-slot LDS ring; the loads of the next two
 //     rows are in flight while a row is computed, and the first wavefront
 //     also pulls the strip's two halo columns.  Solid nodes are not
 //     stored.  Boundary nodes (and the x_f nodes that MLS reads) save their
-//     moments and stored rest population, and under Zhao-Yong their
-//     pre-collision populations, for the next step.  Each workgroup writes
-//     one FP64 partial of the total mass; the first workgroup of the next
-//     launch reduces them in a fixed order.
-//
-// The batched form runs the same two phases as two launches per step
-// (k_boundary_batch, k_main_batch) over all its instances.
+//     moments, and under Zhao-Yong their pre-collision populations, for the
+//     next k_boundary.  Each workgroup writes one FP64 partial of the total
+//     mass; the next launch reduces the partials in a fixed order.
 #pragma once
 
 #include "lattice.hpp"
@@ -52,64 +46,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// ---------------------------------------------------------------- boundary
-enum : int {
-    LK_HALFWAY = 0,  // f*_a(x_b) - wall
-    LK_CHI_UB = 1,   // Eq. 7/8 with u_s = u_b            (FH q < 1/2)
-    LK_CHI_UF = 2,   // Eq. 7/8 with u_s = u_f            (MLS q < 1/2)
-    LK_CHI_EXT = 3,  // Eq. 7/8 with u_s of Eq. 10        (q >= 1/2)
-    LK_LIN_F = 4,    // c1 f*_a(x_b) + c2 f*_a(x_f)
-    LK_LIN_B = 5,    // c1 f*_a(x_b) + c2 f*_abar(x_b)
-    LK_QUAD_F = 6,   // c1 f*_a(x_b) + c2 f*_a(x_f) - c3 f*_a(x_ff)
-    LK_QUAD_B = 7,   // c1 f*_a(x_b) + c2 f*_abar(x_b) - c3 f*_abar(x_f)
-    LK_ZY = 8        // c1 f*_abar(x_b) + c2 f_a(x_b)
-};
-
-// One lane per cut link.  Links are grouped by boundary node (directions
-// ascending) and the groups are padded so that none straddles a
-// workgroup; per-node sums are taken by the group's first lane from LDS in
-// link order.
-struct BndArgs {
-    int nslot;                       // link slots, padding included
-    const int* __restrict__ lnode;   // x_b (pitch layout)
-    const int* __restrict__ lmeta;   // dir | kind << 4 | len << 8 | pos << 12
-    const int* __restrict__ lghost;  // solid neighbour x_s
-    const int* __restrict__ lxf;     // x_f (or -1)
-    const int* __restrict__ lxff;    // x_ff (or -1)
-    const int* __restrict__ lslotb;  // side slot of x_b
-    const int* __restrict__ lslotf;  // side slot of x_f (or -1)
-    const double* __restrict__ lc;   // [slot][8]: c1 c2 c3 chi cb uwq_x uwq_y pad
-    const double* __restrict__ luw;  // [slot][2]: wall velocity
-    // saved by the main pass that produced the populations read here:
-    // [slot][4] rho, u_x, u_y and the stored rest population f*_0 of
-    // boundary nodes (and of the x_f nodes MLS reads); [slot][9] the
-    // pre-collision populations of boundary nodes (Zhao-Yong)
-    const double* __restrict__ side_mom;
-    const double* __restrict__ side_f;
-    long long plane;
-    double rref;                     // deviation storage reference (else 0)
-    const int* __restrict__ lref;    // DEV 2: side slot whose density encodes
-                                     // the ghost (one boundary node per ghost)
-    int fix;                         // 0 none, 1 A, 2 B, 3 Bao
-    // reduction of the previous main pass's mass partials
-    const double* __restrict__ partial;
-    int np;
-    double* __restrict__ hist;
-    long long slot, t;
-    long long* __restrict__ unstable;
-    int do_reduce;
-    // force on the walls (Sec. 4.2, momentum exchange): two FP64 partials
-    // per tile (null: not formed)
-    double* __restrict__ force;
-    // open x boundaries (Sec. 4.2)
-    int open_x;
-    int nx, ny, pitch;
-    double inlet_u;
-};
-
 template <typename S>
 struct MainArgs {
-    const S* src;  // a fused pass also writes ghosts into it (no restrict)
+    const S* __restrict__ src;
     S* __restrict__ dst;
     const uint8_t* __restrict__ flags;  // per node (pitch layout)
     const int* __restrict__ side_idx;   // per node, flagged only
@@ -122,17 +61,6 @@ struct MainArgs {
     long long plane;                    // elements per population plane
     int tile_h, nsegs, nstrips;
     unsigned side_mom_bytes, side_f_bytes;
-    // Fused boundary pass (single-domain steps): before its rows, a tile
-    // evaluates the cut links whose boundary node it pulls (its own rows
-    // and columns and the halo ones), writes their ghosts into src, and
-    // sets the open-boundary slots it pulls.  Links near a tile edge are
-    // evaluated by every tile that pulls their node: each writes the same
-    // values, computed only from data no tile writes in this pass.
-    int fused;
-    BndArgs bnd;                      // side arrays read: the previous pass's
-    const int* __restrict__ tl_off;   // [tiles + 1] chunk range of each tile
-    const int* __restrict__ tl_link;  // [chunks][blockDim.x]: link index, bit
-                                      // 30 set if the tile owns x_b; -1 idle
 };
 
 // Buffer resources: a 32-bit byte range on an SGPR base, so that a load
@@ -195,258 +123,6 @@ struct RowLoad {
     int si;        // side slot (boundary nodes)
     float rr[NR];  // densities of the nine source nodes (DEV 2)
     float pw;      // FP16 storage: psi_w of a solid node in FP32
-};
-
-// Sum a main pass's partials in a fixed order into the history ring:
-// 256 lane sums (lane v adds partials v, v + 256, ... in that order), then
-// a tree over the 256, whatever the workgroup size.  red: 256 doubles.
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ partial,
-                                                int np, double* __restrict__ hist,
-                                                long long slot, long long t,
-                                                long long* __restrict__ unstable,
-                                                double* red) {
-    const int tid = threadIdx.x, W = blockDim.x;
-    for (int v = tid; v < 256; v += W) {
-        // eight loads are issued before their additions
-        double s = 0.0;
-        int i = v;
-        for (; i + 7 * 256 < np; i += 8 * 256) {
-            double q[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) q[j] = partial[i + j * 256];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) s += q[j];
-        }
-        for (; i < np; i += 256) s += partial[i];
-        red[v] = s;
-    }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        for (int v = tid; v < s; v += W) red[v] += red[v + s];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const double m = red[0];
-        hist[slot] = m;
-        if (!isfinite(m) && *unstable < 0) *unstable = t;
-    }
-}
-
-template <int Unused = 0>
-__global__ __launch_bounds__(256) void k_reduce(const double* partial, int np,
-                                                double* hist, long long slot,
-                                                long long t, long long* unstable) {
-    __shared__ double red[256];
-    reduce_partials(partial, np, hist, slot, t, unstable, red);
-}
-
-constexpr int LK_PAD = 15;
-
-// One chunk of cut links, one per lane: link i (i < 0: the lane is idle).
-// Links come grouped by boundary node (directions ascending) and no group
-// straddles a chunk; the per-node sums are taken by the group's first lane
-// from LDS in link order.  lds holds 8 x blockDim.x doubles.  With
-// b.force set, lane 0 adds the momentum of the links marked `owner` to
-// (fx, fy), summed over the chunk by a fixed tree.
-//
-// Reads only populations of fluid nodes and the side arrays; writes only
-// ghost slots, ghost densities (DEV 2) and, for scheme A, the rest slot of
-// x_b from its saved value: evaluating a link twice writes the same values.
-template <typename S, int DEV>
-__device__ __forceinline__ void link_chunk(S* __restrict__ A, const BndArgs& b, int i,
-                                           bool owner, double* lds, double& fx, double& fy) {
-    const int tid = threadIdx.x, W = blockDim.x;
-    double* const s_fab = lds;
-    double* const s_inc = lds + W;
-    double* const s_chi = lds + 2 * W;
-    double* const s_br = lds + 3 * W;
-    double* const s_wall = lds + 4 * W;
-    double* const s_rhos = lds + 5 * W;
-    double* const s_fx = lds + 6 * W;
-    double* const s_fy = lds + 7 * W;
-    const int meta = i >= 0 ? b.lmeta[i] : (LK_PAD << 4);
-    const int d = meta & 15, kind = (meta >> 4) & 15;
-    const int len = (meta >> 8) & 15, pos = (meta >> 12) & 15;
-    const bool active = kind != LK_PAD;
-    const long long P = b.plane;
-    // stored form -> population
-    // DEV 2: densities of the nodes, after the nine population planes
-    float* const rpl = reinterpret_cast<float*>(A + 9 * P);
-    auto ld = [&](int q, int n) {
-        if constexpr (DEV == 2) return double(A[q * P + n]) + wt(q) * double(rpl[n]);
-        return DEV == 1 ? double(A[q * P + n]) + wt(q) * b.rref : double(A[q * P + n]);
-    };
-    int node = 0;
-    double fab = 0.0, r = 0.0, ch = 0.0, bk = 0.0, wl = 0.0;
-    if (active) {
-        node = b.lnode[i];
-        const int od = opp(d);
-        const double* c = b.lc + 8 * i;
-        const double* mom = b.side_mom + 4 * b.lslotb[i];
-        const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
-        const double ex = double(cx(d)), ey = double(cy(d));
-        fab = ld(d, node);
-        const double uwx = b.luw[2 * i], uwy = b.luw[2 * i + 1];
-        // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
-        wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
-        if (kind == LK_HALFWAY) {
-            r = fab - wl;
-        } else if (kind <= LK_CHI_EXT) {
-            double usx, usy;
-            if (kind == LK_CHI_UB) {
-                usx = ubx;
-                usy = uby;
-            } else if (kind == LK_CHI_UF) {
-                const double* mf = b.side_mom + 4 * b.lslotf[i];
-                usx = mf[1];
-                usy = mf[2];
-            } else {
-                usx = c[4] * ubx + c[5];
-                usy = c[4] * uby + c[6];
-            }
-            ch = c[3];
-            // Eq. (8): w_a [1 + 3 e.u_s + 4.5 (e.u_b)^2 - 1.5 u_b^2]
-            const double eus = edot<double>(d, usx, usy);
-            const double eub = edot<double>(d, ubx, uby);
-            const double ub2 = ubx * ubx + uby * uby;
-            bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
-            r = (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
-        } else if (kind == LK_LIN_F) {
-            r = c[0] * fab + c[1] * ld(d, b.lxf[i]);
-        } else if (kind == LK_LIN_B) {
-            r = c[0] * fab + c[1] * ld(od, node);
-        } else if (kind == LK_QUAD_F) {
-            r = c[0] * fab + c[1] * ld(d, b.lxf[i]) - c[2] * ld(d, b.lxff[i]);
-        } else if (kind == LK_QUAD_B) {
-            r = c[0] * fab + c[1] * ld(od, node) - c[2] * ld(od, b.lxf[i]);
-        } else {  // LK_ZY, Eq. (14)
-            r = c[0] * ld(od, node) + c[1] * b.side_f[9 * b.lslotb[i] + d];
-        }
-    }
-    s_fab[tid] = fab;
-    s_inc[tid] = r;
-    s_chi[tid] = ch;
-    s_br[tid] = bk;
-    s_wall[tid] = wl;
-    __syncthreads();
-    const bool head = active && pos == 0;
-    const int h = tid - pos;
-    if (b.fix == 2 || b.fix == 3) {
-        // scheme B, Eq. 22 (chi inside the sums) or Bao et al., Eq. 23
-        if (head) {
-            double num = 0.0, den = 0.0, mag = 0.0;
-            for (int m = 0; m < len; ++m) {
-                if (b.fix == 2) {
-                    num += s_chi[tid + m] * s_fab[tid + m];
-                    den += s_chi[tid + m] * s_br[tid + m];
-                    mag += fabs(s_chi[tid + m] * s_br[tid + m]);
-                } else {
-                    num += s_fab[tid + m];
-                    den += s_br[tid + m];
-                    mag += fabs(s_br[tid + m]);
-                }
-            }
-            s_rhos[tid] = (den != 0.0 && fabs(den) > 1e-12 * mag) ? num / den : NAN;
-        }
-        __syncthreads();
-        if (active) {
-            const double rho_s = s_rhos[h];
-            if (!isnan(rho_s)) {
-                r = (1.0 - ch) * fab + ch * (rho_s * bk) - wl;
-                s_inc[tid] = r;
-            }
-        }
-        __syncthreads();
-    }
-    if (active) {
-        const int g = b.lghost[i];
-        double enc = DEV == 1 ? wt(d) * b.rref : 0.0;
-        if constexpr (DEV == 2) {
-            // every link into ghost g encodes against the same density: that
-            // of one boundary node next to it
-            const float rg = float(b.side_mom[4 * b.lref[i]]);
-            rpl[g] = rg;
-            enc = wt(d) * double(rg);
-        }
-        A[opp(d) * P + g] = S(r - enc);
-    }
-    if (head && b.fix == 1) {
-        // Eq. (15) without the wall momentum, added to the stored rest
-        // population (Eq. 18)
-        double out_sum = 0.0, in_sum = 0.0;
-        for (int m = 0; m < len; ++m) {
-            out_sum += s_fab[tid + m];
-            in_sum += s_inc[tid + m] + s_wall[tid + m];
-        }
-        A[node] = S(b.side_mom[4 * b.lslotb[i] + 3] + (out_sum - in_sum));
-    }
-    if (b.force) {
-        // momentum handed to the wall by the link, e_a (f*_a + f_abar(t+1))
-        const double m = fab + r;
-        s_fx[tid] = (active && owner) ? double(cx(d)) * m : 0.0;
-        s_fy[tid] = (active && owner) ? double(cy(d)) * m : 0.0;
-        __syncthreads();
-        for (int w = W >> 1; w > 0; w >>= 1) {
-            if (tid < w) {
-                s_fx[tid] += s_fx[tid + w];
-                s_fy[tid] += s_fy[tid + w];
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            fx += s_fx[0];
-            fy += s_fy[0];
-        }
-    }
-}
-
-// Open x boundaries (Sec. 4.2) on row y.  The seam between columns nx - 1
-// and 0 is cut: the populations a node there pulls across it are written
-// into the slots it pulls them from.  Both read only slots that no
-// boundary work writes (no wall lies within three columns of the seam).
-//   inlet, x = 0: velocity (U, 0) by the scheme of Zou and He (1997); the
-//     node's density follows from the six populations that arrive from the
-//     interior, and f1, f5, f8 are set so that its moments give (U, 0).
-//   outlet, x = nx - 1: fully developed flow, f3, f6, f7 equal to those of
-//     the node at nx - 2.
-template <typename S, int DEV>
-struct OpenRow {
-    S* A;
-    const BndArgs& b;
-    __device__ double ref(int q, long long n) const {
-        if constexpr (DEV == 2)
-            return wt(q) * double(reinterpret_cast<const float*>(A + 9 * b.plane)[n]);
-        return DEV == 1 ? wt(q) * b.rref : 0.0;
-    }
-    __device__ double ld(int q, long long n) const {
-        return double(A[q * b.plane + n]) + ref(q, n);
-    }
-    __device__ void st(int q, long long n, double v) const {
-        A[q * b.plane + n] = S(v - ref(q, n));
-    }
-    __device__ void inlet(int y) const {
-        const long long p = b.pitch, e = b.nx - 1;
-        const long long r0 = y * p;
-        const long long rm = (y == 0 ? b.ny - 1 : y - 1) * p;
-        const long long rp = (y == b.ny - 1 ? 0 : y + 1) * p;
-        // populations of (0, y) after streaming, each where the pull reads it
-        const double f0 = ld(0, r0), f2 = ld(2, rm), f4 = ld(4, rp);
-        const double f3 = ld(3, r0 + 1), f6 = ld(6, rm + 1), f7 = ld(7, rp + 1);
-        const double U = b.inlet_u;
-        const double rho = (f0 + f2 + f4 + 2.0 * (f3 + f6 + f7)) / (1.0 - U);
-        const double hd = 0.5 * (f2 - f4), s6 = 1.0 / 6.0 * rho * U;
-        st(1, r0 + e, f3 + 2.0 / 3.0 * rho * U);
-        st(5, rm + e, f7 - hd + s6);
-        st(8, rp + e, f6 + hd + s6);
-    }
-    // (nx-1, y) pulls f3, f6, f7 through (0, y), (0, y-1), (0, y+1); this
-    // writes row y of the three planes
-    __device__ void outlet(int y) const {
-        const long long r0 = (long long)y * b.pitch, e = b.nx - 1;
-        st(3, r0, ld(3, r0 + e));
-        st(6, r0, ld(6, r0 + e));
-        st(7, r0, ld(7, r0 + e));
-    }
 };
 
 // Columns a strip updates: a workgroup of tile_w lanes also pulls the
@@ -521,39 +197,6 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         y = y >= a.ny ? y - a.ny : y;
         return y;
     };
-
-    if constexpr (!MOMENTS) {
-        if (a.fused) {
-            // boundary work of this step for the nodes the tile pulls
-            extern __shared__ double dyn[];  // 8 x W doubles
-            S* const cur = const_cast<S*>(a.src);
-            const BndArgs& bn = a.bnd;
-            if (blockIdx.x == 0 && bn.do_reduce)
-                reduce_partials(bn.partial, bn.np, bn.hist, bn.slot, bn.t, bn.unstable, dyn);
-            double fx = 0.0, fy = 0.0;
-            const int c1 = a.tl_off[tile + 1];
-            for (int c = a.tl_off[tile]; c < c1; ++c) {
-                __syncthreads();  // the LDS is free again
-                const int e = a.tl_link[c * W + tid];
-                link_chunk<S, DEV>(cur, bn, e < 0 ? -1 : (e & 0x3fffffff), e >= 0 && (e >> 30),
-                                   dyn, fx, fy);
-            }
-            if (bn.force && tid == 0) {
-                bn.force[2 * tile] = fx;
-                bn.force[2 * tile + 1] = fy;
-            }
-            if (bn.open_x && (strip == 0 || strip == a.nstrips - 1)) {
-                const OpenRow<S, DEV> o{cur, bn};
-                for (int r = tid; r < H + 2; r += W) {
-                    int y = y0 - 1 + r;
-                    y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
-                    if (strip == 0) o.inlet(y);
-                    if (strip == a.nstrips - 1) o.outlet(y);
-                }
-            }
-            __syncthreads();  // ghosts and open slots are written before any pull
-        }
-    }
 
     // flags of the next row to issue are loaded one issue ahead
     uint8_t nfl;
@@ -679,7 +322,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             }
             msum += live ? rho_d : 0.0;
             // moments of boundary nodes (and pre-collision populations)
-            const unsigned so = (live && (Lc.fl & FL_SAVE_MOM)) ? (unsigned)Lc.si * 32u : kOOB;
+            const unsigned so = (live && (Lc.fl & FL_SAVE_MOM)) ? (unsigned)Lc.si * 24u : kOOB;
             bstore(rho_d, rsm, so, 0u);
             bstore(double(ux), rsm, so + 8u, 0u);
             bstore(double(uy), rsm, so + 16u, 0u);
@@ -701,13 +344,6 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
                 const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(Lc.rr[q % NR]) - rho)) + dh[q]
                                      : fc[q] + dh[q];
                 bstore(S(v), rd, vo, q * pb + r0);
-                if (q == 0) {
-                    // the stored rest population, which scheme A corrects
-                    // in the next step
-                    const unsigned s3 = (live && (Lc.fl & FL_SAVE_MOM)) ? (unsigned)Lc.si * 32u + 24u
-                                                                         : kOOB;
-                    bstore(double(S(v)), rsm, s3, 0u);
-                }
             }
             if constexpr (DEV == 2)
                 bstore(float(rho), rd, live ? x * 4u : kOOB, rbase + (unsigned)y * pitch * 4u);
@@ -748,6 +384,303 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
 template <typename S, typename R, int EOS, bool MOMENTS, int DEV, bool SAVEF>
 __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
     main_tile<S, R, EOS, MOMENTS, DEV, SAVEF>(a, ph, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Sum the main kernel's partials in a fixed order into the history ring.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partial,
+                                                int np, double* __restrict__ hist,
+                                                long long slot, long long t,
+                                                long long* __restrict__ unstable) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    // each thread adds partials tid, tid + 256, ... in that order; eight
+    // loads are issued before their additions
+    double v = 0.0;
+    int i = tid;
+    for (; i + 7 * 256 < np; i += 8 * 256) {
+        double q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = partial[i + j * 256];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v += q[j];
+    }
+    for (; i < np; i += 256) v += partial[i];
+    red[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double m = red[0];
+        hist[slot] = m;
+        if (!isfinite(m) && *unstable < 0) *unstable = t;
+    }
+}
+
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_reduce(const double* partial, int np,
+                                                double* hist, long long slot,
+                                                long long t, long long* unstable) {
+    reduce_partials(partial, np, hist, slot, t, unstable);
+}
+
+// ---------------------------------------------------------------- boundary
+enum : int {
+    LK_HALFWAY = 0,  // f*_a(x_b) - wall
+    LK_CHI_UB = 1,   // Eq. 7/8 with u_s = u_b            (FH q < 1/2)
+    LK_CHI_UF = 2,   // Eq. 7/8 with u_s = u_f            (MLS q < 1/2)
+    LK_CHI_EXT = 3,  // Eq. 7/8 with u_s of Eq. 10        (q >= 1/2)
+    LK_LIN_F = 4,    // c1 f*_a(x_b) + c2 f*_a(x_f)
+    LK_LIN_B = 5,    // c1 f*_a(x_b) + c2 f*_abar(x_b)
+    LK_QUAD_F = 6,   // c1 f*_a(x_b) + c2 f*_a(x_f) - c3 f*_a(x_ff)
+    LK_QUAD_B = 7,   // c1 f*_a(x_b) + c2 f*_abar(x_b) - c3 f*_abar(x_f)
+    LK_ZY = 8        // c1 f*_abar(x_b) + c2 f_a(x_b)
+};
+
+// One lane per cut link.  Links are grouped by boundary node (directions
+// ascending) and the groups are padded so that none straddles a
+// workgroup; per-node sums are taken by the group's first lane from LDS in
+// link order.
+struct BndArgs {
+    int nslot;                       // link slots, padding included
+    const int* __restrict__ lnode;   // x_b (pitch layout)
+    const int* __restrict__ lmeta;   // dir | kind << 4 | len << 8 | pos << 12
+                                     // | (DEV 2: sets the ghost's density) << 16
+    const int* __restrict__ lghost;  // solid neighbour x_s
+    const int* __restrict__ lxf;     // x_f (or -1)
+    const int* __restrict__ lxff;    // x_ff (or -1)
+    const int* __restrict__ lslotb;  // side slot of x_b
+    const int* __restrict__ lslotf;  // side slot of x_f (or -1)
+    const double* __restrict__ lc;   // [slot][8]: c1 c2 c3 chi cb uwq_x uwq_y pad
+    const double* __restrict__ luw;  // [slot][2]: wall velocity
+    const double* __restrict__ side_mom;
+    const double* __restrict__ side_f;
+    long long plane;
+    double rref;                     // deviation storage reference (else 0)
+    const int* __restrict__ lref;    // DEV 2: side slot whose density encodes
+                                     // the ghost (one boundary node per ghost)
+    int fix;                         // 0 none, 1 A, 2 B, 3 Bao
+    // reduction of the previous main launch's mass partials (last block)
+    const double* __restrict__ partial;
+    int np;
+    double* __restrict__ hist;
+    long long slot, t;
+    long long* __restrict__ unstable;
+    int do_reduce;
+    // force on the walls (Sec. 4.2, momentum exchange): two FP64 partials
+    // per link block (null: not formed)
+    double* __restrict__ force;
+    // open x boundaries (Sec. 4.2): blocks nlink_blocks .. of the grid take
+    // one row each lane
+    int nlink_blocks;
+    int open_x;
+    int nx, ny, pitch;
+    double inlet_u;
+};
+
+constexpr int LK_PAD = 15;
+
+// Block `blk` of 256 link slots.
+template <typename S, int DEV>
+__device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs& b,
+                                               int blk) {
+    __shared__ double s_fab[256], s_inc[256], s_chi[256], s_br[256], s_wall[256];
+    __shared__ double s_rhos[256];
+    const int tid = threadIdx.x;
+    const int i = blk * 256 + tid;
+    const int meta = i < b.nslot ? b.lmeta[i] : (LK_PAD << 4);
+    const int d = meta & 15, kind = (meta >> 4) & 15;
+    const int len = (meta >> 8) & 15, pos = (meta >> 12) & 15;
+    const bool active = kind != LK_PAD;
+    const long long P = b.plane;
+    // stored form -> population
+    // DEV 2: densities of the nodes, after the nine population planes
+    float* const rpl = reinterpret_cast<float*>(A + 9 * P);
+    auto ld = [&](int q, int n) {
+        if constexpr (DEV == 2) return double(A[q * P + n]) + wt(q) * double(rpl[n]);
+        return DEV == 1 ? double(A[q * P + n]) + wt(q) * b.rref : double(A[q * P + n]);
+    };
+    int node = 0;
+    double fab = 0.0, r = 0.0, ch = 0.0, bk = 0.0, wl = 0.0;
+    if (active) {
+        node = b.lnode[i];
+        const int od = opp(d);
+        const double* c = b.lc + 8 * i;
+        const double* mom = b.side_mom + 3 * b.lslotb[i];
+        const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
+        const double ex = double(cx(d)), ey = double(cy(d));
+        fab = ld(d, node);
+        const double uwx = b.luw[2 * i], uwy = b.luw[2 * i + 1];
+        // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
+        wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
+        if (kind == LK_HALFWAY) {
+            r = fab - wl;
+        } else if (kind <= LK_CHI_EXT) {
+            double usx, usy;
+            if (kind == LK_CHI_UB) {
+                usx = ubx;
+                usy = uby;
+            } else if (kind == LK_CHI_UF) {
+                const double* mf = b.side_mom + 3 * b.lslotf[i];
+                usx = mf[1];
+                usy = mf[2];
+            } else {
+                usx = c[4] * ubx + c[5];
+                usy = c[4] * uby + c[6];
+            }
+            ch = c[3];
+            // Eq. (8): w_a [1 + 3 e.u_s + 4.5 (e.u_b)^2 - 1.5 u_b^2]
+            const double eus = edot<double>(d, usx, usy);
+            const double eub = edot<double>(d, ubx, uby);
+            const double ub2 = ubx * ubx + uby * uby;
+            bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
+            r = (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
+        } else if (kind == LK_LIN_F) {
+            r = c[0] * fab + c[1] * ld(d, b.lxf[i]);
+        } else if (kind == LK_LIN_B) {
+            r = c[0] * fab + c[1] * ld(od, node);
+        } else if (kind == LK_QUAD_F) {
+            r = c[0] * fab + c[1] * ld(d, b.lxf[i]) - c[2] * ld(d, b.lxff[i]);
+        } else if (kind == LK_QUAD_B) {
+            r = c[0] * fab + c[1] * ld(od, node) - c[2] * ld(od, b.lxf[i]);
+        } else {  // LK_ZY, Eq. (14)
+            r = c[0] * ld(od, node) + c[1] * b.side_f[9 * b.lslotb[i] + d];
+        }
+    }
+    s_fab[tid] = fab;
+    s_inc[tid] = r;
+    s_chi[tid] = ch;
+    s_br[tid] = bk;
+    s_wall[tid] = wl;
+    __syncthreads();
+    const bool head = active && pos == 0;
+    const int h = tid - pos;
+    if (b.fix == 2 || b.fix == 3) {
+        // scheme B, Eq. 22 (chi inside the sums) or Bao et al., Eq. 23
+        if (head) {
+            double num = 0.0, den = 0.0, mag = 0.0;
+            for (int m = 0; m < len; ++m) {
+                if (b.fix == 2) {
+                    num += s_chi[tid + m] * s_fab[tid + m];
+                    den += s_chi[tid + m] * s_br[tid + m];
+                    mag += fabs(s_chi[tid + m] * s_br[tid + m]);
+                } else {
+                    num += s_fab[tid + m];
+                    den += s_br[tid + m];
+                    mag += fabs(s_br[tid + m]);
+                }
+            }
+            s_rhos[tid] = (den != 0.0 && fabs(den) > 1e-12 * mag) ? num / den : NAN;
+        }
+        __syncthreads();
+        if (active) {
+            const double rho_s = s_rhos[h];
+            if (!isnan(rho_s)) {
+                r = (1.0 - ch) * fab + ch * (rho_s * bk) - wl;
+                s_inc[tid] = r;
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        const int g = b.lghost[i];
+        double enc = DEV == 1 ? wt(d) * b.rref : 0.0;
+        if constexpr (DEV == 2) {
+            // every link into ghost g encodes against the same density: that
+            // of one boundary node next to it, which one of them records
+            const float rg = float(b.side_mom[3 * b.lref[i]]);
+            if ((meta >> 16) & 1) rpl[g] = rg;
+            enc = wt(d) * double(rg);
+        }
+        A[opp(d) * P + g] = S(r - enc);
+    }
+    if (head && b.fix == 1) {
+        // Eq. (15) without the wall momentum, added to the rest population
+        // (Eq. 18)
+        double out_sum = 0.0, in_sum = 0.0;
+        for (int m = 0; m < len; ++m) {
+            out_sum += s_fab[tid + m];
+            in_sum += s_inc[tid + m] + s_wall[tid + m];
+        }
+        A[node] = S(double(A[node]) + (out_sum - in_sum));
+    }
+    if (b.force) {
+        // momentum handed to the wall by this link, e_a (f*_a + f_abar(t+1)),
+        // summed over the block by a fixed tree
+        __shared__ double s_fx[256], s_fy[256];
+        const double m = fab + r;
+        s_fx[tid] = active ? double(cx(d)) * m : 0.0;
+        s_fy[tid] = active ? double(cy(d)) * m : 0.0;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) {
+                s_fx[tid] += s_fx[tid + w];
+                s_fy[tid] += s_fy[tid + w];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            b.force[2 * blk] = s_fx[0];
+            b.force[2 * blk + 1] = s_fy[0];
+        }
+    }
+}
+
+// Open x boundaries (Sec. 4.2), lane y of block `blk` takes row y.  The
+// seam between columns nx-1 and 0 is cut: the populations a node there
+// pulls across it are written into the slots it pulls them from.
+//   inlet, x = 0: velocity (U, 0) by the scheme of Zou and He (1997); the
+//     node's density follows from the six populations that arrive from the
+//     interior, and f1, f5, f8 are set so that its moments give (U, 0).
+//   outlet, x = nx - 1: fully developed flow, f3, f6, f7 equal to those of
+//     the node at nx - 2.
+// No cut link reads or writes these slots (the three outermost columns on
+// each side are fluid), so the rows run beside the link blocks.
+template <typename S, int DEV>
+__device__ __forceinline__ void open_rows(S* __restrict__ A, const BndArgs& b, int blk) {
+    const int y = blk * 256 + int(threadIdx.x);
+    if (y >= b.ny) return;
+    const long long P = b.plane;
+    float* const rpl = reinterpret_cast<float*>(A + 9 * P);
+    auto ref = [&](int q, long long n) {
+        if constexpr (DEV == 2) return wt(q) * double(rpl[n]);
+        return DEV == 1 ? wt(q) * b.rref : 0.0;
+    };
+    auto ld = [&](int q, long long n) { return double(A[q * P + n]) + ref(q, n); };
+    auto st = [&](int q, long long n, double v) { A[q * P + n] = S(v - ref(q, n)); };
+    const long long p = b.pitch, e = b.nx - 1;
+    const long long r0 = y * p;
+    const long long rm = (y == 0 ? b.ny - 1 : y - 1) * p;
+    const long long rp = (y == b.ny - 1 ? 0 : y + 1) * p;
+    // populations of (0, y) after streaming, each where the pull reads it
+    const double f0 = ld(0, r0), f2 = ld(2, rm), f4 = ld(4, rp);
+    const double f3 = ld(3, r0 + 1), f6 = ld(6, rm + 1), f7 = ld(7, rp + 1);
+    const double U = b.inlet_u;
+    const double rho = (f0 + f2 + f4 + 2.0 * (f3 + f6 + f7)) / (1.0 - U);
+    const double h = 0.5 * (f2 - f4), s6 = 1.0 / 6.0 * rho * U;
+    st(1, r0 + e, f3 + 2.0 / 3.0 * rho * U);
+    st(5, rm + e, f7 - h + s6);
+    st(8, rp + e, f6 + h + s6);
+    // outlet: (nx-1, y) pulls f3, f6, f7 through (0, y), (0, y-1), (0, y+1);
+    // lane y fills row y of the three planes
+    st(3, r0, ld(3, r0 + e));
+    st(6, r0, ld(6, r0 + e));
+    st(7, r0, ld(7, r0 + e));
+}
+
+// The last block reduces the previous main pass's mass partials.
+template <typename S, int DEV>
+__global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
+    if (blockIdx.x == gridDim.x - 1) {
+        if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
+        return;
+    }
+    if (int(blockIdx.x) >= b.nlink_blocks) {
+        open_rows<S, DEV>(A, b, blockIdx.x - b.nlink_blocks);
+        return;
+    }
+    boundary_block<S, DEV>(A, b, blockIdx.x);
 }
 
 // f(0) = f_eq(rho0, u0), stored where the first pull reads it:
@@ -871,9 +804,6 @@ __device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long 
     a.nstrips = I.nstrips;
     a.side_mom_bytes = I.side_mom_bytes;
     a.side_f_bytes = I.side_f_bytes;
-    a.fused = 0;  // the batch runs its boundary pass as a launch of its own
-    a.tl_off = nullptr;
-    a.tl_link = nullptr;
     return a;
 }
 
@@ -926,7 +856,6 @@ __global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
 
 template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
-    __shared__ double lds[8 * 256];
     const int n = *b.nlblk;
     for (int k = blockIdx.x; k < n; k += gridDim.x) {
         const int2 e = b.lblk[k];
@@ -958,15 +887,12 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.unstable = nullptr;
         a.do_reduce = 0;
         a.force = nullptr;
+        a.nlink_blocks = 0;
         a.open_x = 0;
         a.nx = a.ny = a.pitch = 0;
         a.inlet_u = 0.0;
         __syncthreads();  // the previous block is done with the LDS
-        // link block e.y of the instance's table: 256 link slots
-        const int i = e.y * 256 + int(threadIdx.x);
-        double fx = 0.0, fy = 0.0;
-        link_chunk<S, DEV>(static_cast<S*>(I.f[st.t & 1]), a, i < a.nslot ? i : -1, false, lds,
-                           fx, fy);
+        boundary_block<S, DEV>(static_cast<S*>(I.f[st.t & 1]), a, e.y);
     }
 }
 
@@ -975,7 +901,6 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
 // unstable).  Also empties the tile queues for the next main pass.
 template <int Unused = 0>
 __global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
-    __shared__ double red[256];
     for (int i = blockIdx.x; i < b.ninst; i += gridDim.x) {
         BState* st = b.state + i;
         const long long rem = st->remaining;
@@ -983,7 +908,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
         const BInst& I = b.inst[i];
         const long long t1 = st->t + 1;
         __syncthreads();
-        reduce_partials(I.partial, I.np, I.hist, t1 % I.cap, t1, I.unstable, red);
+        reduce_partials(I.partial, I.np, I.hist, t1 % I.cap, t1, I.unstable);
         if (threadIdx.x == 0) {
             st->t = t1;
             st->remaining = *I.unstable >= 0 ? 0 : rem - 1;

@@ -27,18 +27,14 @@ struct Ctx {
     const float* ref;  // init: density plane of the buffer being filled (or null)
     Phys<double> ph;  // converted to the compute type by the launcher
     hipStream_t stream;
-    // fused boundary pass (see MainArgs): link tables, side arrays read,
-    // reduction of the previous partials, force and open boundaries
-    int fused;
-    BndArgs bnd;
-    const int* tl_off;
-    const int* tl_link;
 };
 
-// one main pass src -> dst (or the moments of src when moments is set);
-// with c.fused the pass first does the step's boundary work on src
+// one main pass src -> dst (or the moments of src when moments is set)
 void launch_main_f64(const Ctx& c, const void* src, void* dst, bool moments);
 void launch_main_f32(const Ctx& c, const void* src, void* dst, bool moments);
+// one boundary pass on cur
+void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
+void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
 // psi at walls into plane 0 of both buffers, and f(0) = f_eq(rho0, u0)
 // scattered into buf
 void launch_init_f64(const Ctx& c, const double* rho_wall, const double* rho0,

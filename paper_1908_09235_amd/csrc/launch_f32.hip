@@ -16,6 +16,14 @@ void launch_main_f32(const Ctx& c, const void* src, void* dst, bool moments) {
     default: main_any<float, double>(c, src, dst, moments);
     }
 }
+void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
+    switch (c.storage) {
+    case 3: boundary_any<float, 1>(c, cur, b, nblocks); break;
+    case 4: boundary_any<_Float16, 1>(c, cur, b, nblocks); break;
+    case 5: boundary_any<_Float16, 2>(c, cur, b, nblocks); break;
+    default: boundary_any<float>(c, cur, b, nblocks);
+    }
+}
 void launch_init_f32(const Ctx& c, const double* rw, const double* r0, const double* u0,
                      const double* v0, void* buf, void* other) {
     switch (c.storage) {

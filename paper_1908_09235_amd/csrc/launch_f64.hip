@@ -7,6 +7,9 @@ namespace lbm {
 void launch_main_f64(const Ctx& c, const void* src, void* dst, bool moments) {
     main_any<double, double>(c, src, dst, moments);
 }
+void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
+    boundary_any<double>(c, cur, b, nblocks);
+}
 void launch_init_f64(const Ctx& c, const double* rw, const double* r0, const double* u0,
                      const double* v0, void* buf, void* other) {
     init_any<double, double>(c, rw, r0, u0, v0, buf, other);

@@ -31,13 +31,7 @@ void main_t(const Ctx& c, const S* src, S* dst) {
     a.nstrips = c.nstrips;
     a.side_mom_bytes = c.side_mom_bytes;
     a.side_f_bytes = c.side_f_bytes;
-    a.fused = (!MOM && c.fused) ? 1 : 0;
-    a.bnd = c.bnd;
-    a.tl_off = c.tl_off;
-    a.tl_link = c.tl_link;
-    // the fused pass keeps eight link arrays of tile_w doubles in LDS
-    const unsigned lds = a.fused ? 8u * (unsigned)c.tile_w * 8u : 0u;
-    hipLaunchKernelGGL((k_main<S, R, EOS, MOM, DEV, SAVEF>), dim3(c.nblocks), dim3(c.tile_w), lds,
+    hipLaunchKernelGGL((k_main<S, R, EOS, MOM, DEV, SAVEF>), dim3(c.nblocks), dim3(c.tile_w), 0,
                        c.stream, a, convert<R>(c.ph));
 }
 
@@ -55,6 +49,12 @@ void main_any(const Ctx& c, const void* src, void* dst, bool moments) {
     if (moments) main_e<S, R, true, DEV, false>(c, s, t);
     else if (c.save_f) main_e<S, R, false, DEV, true>(c, s, t);
     else main_e<S, R, false, DEV, false>(c, s, t);
+}
+
+template <typename S, int DEV = 0>
+void boundary_any(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
+    hipLaunchKernelGGL((k_boundary<S, DEV>), dim3(nblocks), dim3(256), 0, c.stream,
+                       static_cast<S*>(cur), b);
 }
 
 template <typename S, typename R>

@@ -17,7 +17,7 @@ using namespace lbm;
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x6c626d3270737432ULL;  // "lbm2pst2"
+constexpr uint64_t kStateMagic = 0x6c626d3270737431ULL;  // "lbm2pst1"
 constexpr int kProfPool = 1024;
 
 }  // namespace
@@ -135,7 +135,7 @@ Ctx ctx(lbm_domain* d) {
     c.psiw = d->psiw;
     c.side_mom = d->side_mom;
     c.side_f = d->side_f;
-    c.side_mom_bytes = (unsigned)(4 * std::max(d->nslots, 1) * 8);
+    c.side_mom_bytes = (unsigned)(3 * std::max(d->nslots, 1) * 8);
     c.side_f_bytes = (unsigned)(9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8);
     c.save_f = d->save_f;
     c.partial = d->partial;
@@ -143,32 +143,16 @@ Ctx ctx(lbm_domain* d) {
     c.ref = nullptr;
     c.ph = d->ph64;
     c.stream = d->stream;
-    c.fused = 0;
-    c.tl_off = d->tl_off;
-    c.tl_link = d->tl_link;
     return c;
 }
 
-// the arrays of parity t (a batch instance has one of each)
-double* sm_of(lbm_domain* d, long long t) { return (t & 1) ? d->side_mom2 : d->side_mom; }
-double* sf_of(lbm_domain* d, long long t) { return (t & 1) ? d->side_f2 : d->side_f; }
-double* part_of(lbm_domain* d, long long t) { return (t & 1) ? d->partial2 : d->partial; }
-
-// a pass producing f*(t) writes the side arrays and partials of parity t
-Ctx ctx_at(lbm_domain* d, long long t) {
-    Ctx c = ctx(d);
-    c.side_mom = sm_of(d, t);
-    c.side_f = sf_of(d, t);
-    c.partial = part_of(d, t);
-    return c;
+void launch_main(lbm_domain* d, const void* src, void* dst, bool moments) {
+    if (d->storage == LBM_STORE_F64) launch_main_f64(ctx(d), src, dst, moments);
+    else launch_main_f32(ctx(d), src, dst, moments);
 }
 
-void launch_main(const Ctx& c, const void* src, void* dst, bool moments) {
-    if (c.storage == LBM_STORE_F64) launch_main_f64(c, src, dst, moments);
-    else launch_main_f32(c, src, dst, moments);
-}
+int link_blocks(const lbm_domain* d) { return (d->nslot_links + 255) / 256; }
 
-// boundary work of step t -> t + 1 (read side arrays of parity t)
 BndArgs bnd_args(lbm_domain* d) {
     BndArgs b{};
     b.nslot = d->nslot_links;
@@ -181,13 +165,13 @@ BndArgs bnd_args(lbm_domain* d) {
     b.lslotf = d->lslotf;
     b.lc = d->lc;
     b.luw = d->luw;
-    b.side_mom = sm_of(d, d->t);
-    b.side_f = sf_of(d, d->t);
+    b.side_mom = d->side_mom;
+    b.side_f = d->side_f;
     b.plane = d->plane;
     b.rref = d->ph64.rref;
     b.lref = d->lref;
     b.fix = d->fix;
-    b.partial = part_of(d, d->pending_t);
+    b.partial = d->partial;
     b.np = d->nblocks;
     b.hist = d->hist;
     b.unstable = d->unstable;
@@ -195,6 +179,7 @@ BndArgs bnd_args(lbm_domain* d) {
     b.t = d->pending_t;
     b.slot = d->pending_t % d->cap;
     b.force = d->force;
+    b.nlink_blocks = link_blocks(d);
     b.open_x = d->open_x;
     b.nx = d->nx;
     b.ny = d->ny;
@@ -203,20 +188,19 @@ BndArgs bnd_args(lbm_domain* d) {
     return b;
 }
 
-// one step: boundary work and main pass in one launch, cur -> nxt
-void launch_step(lbm_domain* d, void* cur, void* nxt) {
-    Ctx c = ctx_at(d, d->t + 1);
-    c.fused = 1;
-    c.bnd = bnd_args(d);
-    launch_main(c, cur, nxt, false);
+void launch_boundary(lbm_domain* d, void* cur) {
+    BndArgs b = bnd_args(d);
+    // link blocks, then the open rows, then the block that reduces
+    const int nbb = b.nlink_blocks + (d->open_x ? (d->ny + 255) / 256 : 0) + 1;
+    if (d->storage == LBM_STORE_F64) launch_boundary_f64(ctx(d), cur, b, nbb);
+    else launch_boundary_f32(ctx(d), cur, b, nbb);
     d->pending = false;
     d->force_valid = true;
 }
 
 void reduce_pending(lbm_domain* d) {
     if (!d->pending) return;
-    launch_reduce(ctx_at(d, d->pending_t), d->pending_t % d->cap, d->pending_t, d->hist,
-                  d->unstable);
+    launch_reduce(ctx(d), d->pending_t % d->cap, d->pending_t, d->hist, d->unstable);
     d->pending = false;
 }
 
@@ -257,11 +241,11 @@ int run_steps(lbm_domain* d, int64_t n) {
             if (rc) return rc;
         }
         hipEvent_t* e = rec ? &d->ev[4 * d->nrec] : nullptr;
-        // (the boundary work is part of the main pass: its interval is empty)
         if (rec) (void)hipEventRecord(e[0], d->stream);
+        launch_boundary(d, cur);
         if (rec) (void)hipEventRecord(e[1], d->stream);
         if (rec) (void)hipEventRecord(e[2], d->stream);
-        launch_step(d, cur, nxt);
+        launch_main(d, cur, nxt, false);
         if (rec) (void)hipEventRecord(e[3], d->stream);
         if (rec) d->nrec++;
         d->cur ^= 1;
@@ -272,77 +256,6 @@ int run_steps(lbm_domain* d, int64_t n) {
     reduce_pending(d);
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     return LBM_OK;
-}
-
-// Per-tile link lists of the fused pass.  A tile lists every cut link
-// whose boundary node it pulls (its own rows and columns and the halo
-// ones), node groups whole within chunks of tile_w entries; bit 30 marks
-// the links of the nodes the tile updates, whose momentum it counts.
-int build_tile_links(lbm_domain* d) {
-    const int W = d->tile_w, ns = d->nstrips, ng = d->nsegs, nx = d->nx, ny = d->ny;
-    const int P = d->pitch, th = d->tile_h;
-    // the columns of strip s, as the main pass splits them
-    std::vector<int> sx0(ns + 1);
-    for (int s = 0; s <= ns; ++s) sx0[s] = (int)(((unsigned long long)s * nx) / ns);
-    std::vector<int> col_strip(nx);
-    for (int s = 0; s < ns; ++s)
-        for (int x = sx0[s]; x < sx0[s + 1]; ++x) col_strip[x] = s;
-    auto pulls_col = [&](int s, int x) {  // columns sx0[s] - 1 .. sx0[s + 1]
-        return wrapi(x - (sx0[s] - 1), nx) <= sx0[s + 1] - sx0[s] + 1;
-    };
-    auto pulls_row = [&](int g, int y) {  // rows y0 - 1 .. y0 + H
-        const int y0 = g * th, H = std::min(th, ny - y0);
-        return wrapi(y - (y0 - 1), ny) <= H + 1;
-    };
-    const int ntiles = ns * ng;
-    std::vector<std::vector<int>> lists((size_t)ntiles);
-    const std::vector<int>& ln = d->h_lnode;
-    const std::vector<int>& lm = d->h_lmeta;
-    for (size_t k0 = 0; k0 < ln.size();) {
-        if (((lm[k0] >> 4) & 15) == LK_PAD) {
-            ++k0;
-            continue;
-        }
-        const int len = (lm[k0] >> 8) & 15;
-        const int x = ln[k0] % P, y = ln[k0] / P;
-        const int so = col_strip[x], go = y / th;
-        int cs[3], cg[3], ncs = 0, ncg = 0;
-        for (int dd = -1; dd <= 1; ++dd) {
-            const int s = wrapi(so + dd, ns), g = wrapi(go + dd, ng);
-            if (pulls_col(s, x) && std::find(cs, cs + ncs, s) == cs + ncs) cs[ncs++] = s;
-            if (pulls_row(g, y) && std::find(cg, cg + ncg, g) == cg + ncg) cg[ncg++] = g;
-        }
-        for (int i = 0; i < ncg; ++i)
-            for (int j = 0; j < ncs; ++j) {
-                std::vector<int>& L = lists[(size_t)cg[i] * ns + cs[j]];
-                const int own = (cg[i] == go && cs[j] == so) ? (1 << 30) : 0;
-                const size_t used = L.size() % W;
-                if (used + len > (size_t)W) L.resize(L.size() + (W - used), -1);
-                for (int m = 0; m < len; ++m) L.push_back((int)(k0 + m) | own);
-            }
-        k0 += len;
-    }
-    std::vector<int> off((size_t)ntiles + 1, 0), links;
-    for (int t = 0; t < ntiles; ++t) {
-        std::vector<int>& L = lists[t];
-        if (L.size() % W) L.resize(L.size() + (W - L.size() % W), -1);
-        off[t + 1] = off[t] + (int)(L.size() / W);
-        links.insert(links.end(), L.begin(), L.end());
-    }
-    if (links.empty()) links.push_back(-1);
-    // queued work may still read the previous lists
-    if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
-    if (d->tl_off) dev_free(d, d->tl_off, d->tl_off_bytes);
-    if (d->tl_link) dev_free(d, d->tl_link, d->tl_link_bytes);
-    d->tl_off = nullptr;
-    d->tl_link = nullptr;
-    int rc;
-    if ((rc = upload(d, &d->tl_off, off))) return rc;
-    if ((rc = upload(d, &d->tl_link, links))) return rc;
-    d->tl_off_bytes = off.size() * sizeof(int);
-    d->tl_link_bytes = links.size() * sizeof(int);
-    // the host vectors go out of scope here
-    return hipStreamSynchronize(d->stream) == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 
 int check_unstable(lbm_domain* d) {
@@ -641,20 +554,23 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (s->storage == LBM_STORE_F16NODE) {
         // Each ghost (a solid node receiving incoming populations) is
         // encoded against the density of one boundary node next to it: the
-        // first in table order.  Every link into the ghost records it.
+        // first in table order, whose link records it.
         std::vector<int> owner((size_t)P * ny, -1);
         lref.assign(lnode.size(), 0);
         for (size_t k = 0; k < lnode.size(); ++k) {
             if (((lmeta[k] >> 4) & 15) == LK_PAD) continue;
             const int g = lghost[k];
-            if (owner[g] < 0) owner[g] = (int)k;
+            if (owner[g] < 0) {
+                owner[g] = (int)k;
+                lmeta[k] |= 1 << 16;
+            }
             lref[k] = lslotb[owner[g]];
         }
         rplane.assign((size_t)d->plane, 0.0f);
         for (long long i = 0; i < N; ++i)
             if (!solid(i)) rplane[pidx((int)(i % nx), (int)(i / nx))] = float(s->rho0[i]);
         for (size_t k = 0; k < lnode.size(); ++k)
-            if (((lmeta[k] >> 4) & 15) != LK_PAD && owner[lghost[k]] == (int)k) {
+            if ((lmeta[k] >> 16) & 1) {
                 const int n = lnode[k];
                 rplane[lghost[k]] = float(s->rho0[(long long)(n / P) * nx + (n % P)]);
             }
@@ -672,25 +588,13 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &d->flags, flags))) return rc;
     if ((rc = upload(d, &d->side_idx, side_idx))) return rc;
     if (d->esize == 2 && (rc = dev_alloc(d, (void**)&d->psiw, (size_t)P * ny * 4))) return rc;
-    // a domain of its own runs its boundary work inside the main pass; an
-    // instance of a batch runs it as a launch of the batch
-    d->fused = d->arena == nullptr;
-    const size_t smb = (size_t)4 * std::max(nslots, 1) * 8;
-    const size_t sfb = (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8;
-    if ((rc = dev_alloc(d, (void**)&d->side_mom, smb))) return rc;
-    if ((rc = dev_alloc(d, (void**)&d->side_f, sfb))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->side_mom, (size_t)3 * std::max(nslots, 1) * 8))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->side_f,
+                        (size_t)9 * (d->save_f ? std::max(nslots, 1) : 1) * 8)))
+        return rc;
     // partials for any tile shape down to 64 x 8 (the batched form retunes)
     d->partial_cap = std::max(d->nblocks, ((nx + strip_cols(64) - 1) / strip_cols(64)) * ((ny + 7) / 8));
     if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->partial_cap * 8))) return rc;
-    if (d->fused) {
-        if ((rc = dev_alloc(d, (void**)&d->side_mom2, smb))) return rc;
-        if ((rc = dev_alloc(d, (void**)&d->side_f2, sfb))) return rc;
-        if ((rc = dev_alloc(d, (void**)&d->partial2, (size_t)d->partial_cap * 8))) return rc;
-    } else {
-        d->side_mom2 = d->side_mom;
-        d->side_f2 = d->side_f;
-        d->partial2 = d->partial;
-    }
     if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
     // in an arena (batched and served instances) the read-out buffer is part
@@ -706,12 +610,9 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = upload(d, &d->lc, lc))) return rc;
     if ((rc = upload(d, &d->luw, luw))) return rc;
     if (!lref.empty() && (rc = upload(d, &d->lref, lref))) return rc;
-    if ((rc = dev_alloc(d, (void**)&d->force, (size_t)2 * d->partial_cap * 8))) return rc;
-    if (d->fused) {
-        d->h_lnode = lnode;
-        d->h_lmeta = lmeta;
-        if ((rc = build_tile_links(d))) return rc;
-    }
+    if ((rc = dev_alloc(d, (void**)&d->force,
+                        (size_t)2 * std::max(link_blocks(d), 1) * 8)))
+        return rc;
 
     const long long minus1 = -1;
     if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
@@ -746,7 +647,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         }
         launch_init_f32(c, drw, dr0, du0, dv0, d->f[1], d->f[0]);
     }
-    launch_main(ctx_at(d, 0), d->f[1], d->f[0], false);
+    launch_main(d, d->f[1], d->f[0], false);
     d->cur = 0;
     d->t = 0;
     d->pending = true;
@@ -790,11 +691,6 @@ int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h) {
     d->nstrips = ns;
     d->nsegs = ng;
     d->nblocks = ns * ng;
-    if (d->fused) {
-        // the next step reduces partials of the old tiling: do it now
-        reduce_pending(d);
-        return build_tile_links(d);
-    }
     return LBM_OK;
 }
 
@@ -892,7 +788,7 @@ int lbm_moments_device(lbm_domain* d, double* rho, double* ux, double* uy) {
         int rc = dev_alloc(d, (void**)&d->mom_out, 3 * nn * 8);
         if (rc) return rc;
     }
-    launch_main(ctx(d), d->f[d->cur ^ 1], nullptr, true);
+    launch_main(d, d->f[d->cur ^ 1], nullptr, true);
     if (rho && hipMemcpyAsync(rho, d->mom_out, nn * 8, hipMemcpyDeviceToDevice, d->stream))
         return LBM_EDEVICE;
     if (ux && hipMemcpyAsync(ux, d->mom_out + nn, nn * 8, hipMemcpyDeviceToDevice, d->stream))
@@ -909,7 +805,7 @@ int lbm_moments(lbm_domain* d, double* rho, double* ux, double* uy) {
         int rc = dev_alloc(d, (void**)&d->mom_out, 3 * nn * 8);
         if (rc) return rc;
     }
-    launch_main(ctx(d), d->f[d->cur ^ 1], nullptr, true);
+    launch_main(d, d->f[d->cur ^ 1], nullptr, true);
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     double* outs[3] = {rho, ux, uy};
     for (int k = 0; k < 3; ++k)
@@ -934,13 +830,13 @@ int lbm_wall_force(lbm_domain* d, double out[2]) {
     if (!d || !out) return LBM_EINVAL;
     out[0] = out[1] = 0.0;
     if (!d->force_valid) return LBM_OK;
-    const int n = d->nblocks;
-    std::vector<double> part((size_t)2 * n, 0.0);
-    if (hipMemcpyAsync(part.data(), d->force, (size_t)2 * n * 8, hipMemcpyDeviceToHost,
-                       d->stream) != hipSuccess)
+    const int n = link_blocks(d);
+    std::vector<double> part((size_t)2 * std::max(n, 1), 0.0);
+    if (n > 0 && hipMemcpyAsync(part.data(), d->force, (size_t)2 * n * 8,
+                                hipMemcpyDeviceToHost, d->stream) != hipSuccess)
         return LBM_EDEVICE;
     if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
-    // tile partials in tile order
+    // block partials in block order
     for (int k = 0; k < n; ++k) {
         out[0] += part[2 * k];
         out[1] += part[2 * k + 1];
@@ -980,7 +876,7 @@ int lbm_unstable_step(lbm_domain* d, int64_t* step) {
 }
 
 static size_t state_bytes(const lbm_domain* d) {
-    return 8 * 4 + 2 * d->fbytes + (size_t)4 * std::max(d->nslots, 1) * 8 +
+    return 8 * 4 + 2 * d->fbytes + (size_t)3 * std::max(d->nslots, 1) * 8 +
            (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8 + (size_t)d->cap * 8 + 8;
 }
 
@@ -999,15 +895,15 @@ int lbm_get_state(lbm_domain* d, void* buf, size_t* bytes) {
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     const size_t fb = d->fbytes;
-    const size_t sm = (size_t)4 * std::max(d->nslots, 1) * 8;
+    const size_t sm = (size_t)3 * std::max(d->nslots, 1) * 8;
     const size_t sf = (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8;
     if (hipMemcpy(p, d->f[d->cur], fb, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
     p += fb;
     if (hipMemcpy(p, d->f[d->cur ^ 1], fb, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
     p += fb;
-    if (hipMemcpy(p, sm_of(d, d->t), sm, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemcpy(p, d->side_mom, sm, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
     p += sm;
-    if (hipMemcpy(p, sf_of(d, d->t), sf, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemcpy(p, d->side_f, sf, hipMemcpyDeviceToHost) != hipSuccess) return LBM_EDEVICE;
     p += sf;
     if (hipMemcpy(p, d->hist, (size_t)d->cap * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return LBM_EDEVICE;
@@ -1028,23 +924,22 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
     p += sizeof(hdr);
     if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
     const size_t fb = d->fbytes;
-    const size_t sm = (size_t)4 * std::max(d->nslots, 1) * 8;
+    const size_t sm = (size_t)3 * std::max(d->nslots, 1) * 8;
     const size_t sf = (size_t)9 * (d->save_f ? std::max(d->nslots, 1) : 1) * 8;
-    const long long t = (long long)hdr[1];
     d->cur = 0;
     if (hipMemcpy(d->f[0], p, fb, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     p += fb;
     if (hipMemcpy(d->f[1], p, fb, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     p += fb;
-    if (hipMemcpy(sm_of(d, t), p, sm, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemcpy(d->side_mom, p, sm, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     p += sm;
-    if (hipMemcpy(sf_of(d, t), p, sf, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemcpy(d->side_f, p, sf, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     p += sf;
     if (hipMemcpy(d->hist, p, (size_t)d->cap * 8, hipMemcpyHostToDevice) != hipSuccess)
         return LBM_EDEVICE;
     p += (size_t)d->cap * 8;
     if (hipMemcpy(d->unstable, p, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
-    d->t = t;
+    d->t = (long long)hdr[1];
     d->pending = false;
     d->pending_t = d->t;
     d->force_valid = false;
