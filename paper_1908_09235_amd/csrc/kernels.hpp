@@ -247,8 +247,11 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             L.pw = bload<float>(rpw, (own && !fluid) ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
         if constexpr (!MOMENTS) {
             // side slot of a boundary node (or of an x_f node of MLS)
+            // (a wavefront with no such node in the row issues nothing)
             const bool side = fluid && (fl & (FL_SAVE_MOM | FL_SAVE_F));
-            L.si = bload<int>(rsi, side ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
+            L.si = 0;
+            if (__builtin_amdgcn_ballot_w64(side))
+                L.si = bload<int>(rsi, side ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
         }
     };
     // stored form -> populations (DEV 2) or the stored form itself
@@ -322,16 +325,25 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             }
             msum += live ? rho_d : 0.0;
             // moments of boundary nodes (and pre-collision populations)
-            const unsigned so = (live && (Lc.fl & FL_SAVE_MOM)) ? (unsigned)Lc.si * 24u : kOOB;
-            bstore(rho_d, rsm, so, 0u);
-            bstore(double(ux), rsm, so + 8u, 0u);
-            bstore(double(uy), rsm, so + 16u, 0u);
+            // (stores only from a wavefront with such a node in the row:
+            // the branch is uniform, and the waits for the rows in flight
+            // stay exact on the path without them)
+            const bool sm = live && (Lc.fl & FL_SAVE_MOM);
+            if (__builtin_amdgcn_ballot_w64(sm)) {
+                const unsigned so = sm ? (unsigned)Lc.si * 24u : kOOB;
+                bstore(rho_d, rsm, so, 0u);
+                bstore(double(ux), rsm, so + 8u, 0u);
+                bstore(double(uy), rsm, so + 16u, 0u);
+            }
             if constexpr (SAVEF) {
-                const unsigned fo = (live && (Lc.fl & FL_SAVE_F)) ? (unsigned)Lc.si * 72u : kOOB;
+                const bool sf = live && (Lc.fl & FL_SAVE_F);
+                if (__builtin_amdgcn_ballot_w64(sf)) {
+                    const unsigned fo = sf ? (unsigned)Lc.si * 72u : kOOB;
 #pragma unroll
-                for (int q = 0; q < 9; ++q)
-                    bstore(DEV == 1 ? double(fc[q]) + wt(q) * double(ph.rref) : double(fc[q]), rsf,
-                           fo + 8u * q, 0u);
+                    for (int q = 0; q < 9; ++q)
+                        bstore(DEV == 1 ? double(fc[q]) + wt(q) * double(ph.rref) : double(fc[q]),
+                               rsf, fo + 8u * q, 0u);
+                }
             }
             R dh[9];
             collide<R>(fc, rho, drho, ux, uy, Fx, Fy, ph, dh);
@@ -607,22 +619,24 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
     }
     if (b.force) {
         // momentum handed to the wall by this link, e_a (f*_a + f_abar(t+1)),
-        // summed over the block by a fixed tree
-        __shared__ double s_fx[256], s_fy[256];
+        // summed in a fixed order: down each wavefront, then the four
+        // wavefront sums
+        __shared__ double s_fx[4], s_fy[4];
         const double m = fab + r;
-        s_fx[tid] = active ? double(cx(d)) * m : 0.0;
-        s_fy[tid] = active ? double(cy(d)) * m : 0.0;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) {
-                s_fx[tid] += s_fx[tid + w];
-                s_fy[tid] += s_fy[tid + w];
-            }
-            __syncthreads();
+        double vx = active ? double(cx(d)) * m : 0.0;
+        double vy = active ? double(cy(d)) * m : 0.0;
+        for (int off = 32; off > 0; off >>= 1) {
+            vx += __shfl_down(vx, off, 64);
+            vy += __shfl_down(vy, off, 64);
         }
+        if ((tid & 63) == 0) {
+            s_fx[tid >> 6] = vx;
+            s_fy[tid >> 6] = vy;
+        }
+        __syncthreads();
         if (tid == 0) {
-            b.force[2 * blk] = s_fx[0];
-            b.force[2 * blk + 1] = s_fy[0];
+            b.force[2 * blk] = (s_fx[0] + s_fx[1]) + (s_fx[2] + s_fx[3]);
+            b.force[2 * blk + 1] = (s_fy[0] + s_fy[1]) + (s_fy[2] + s_fy[3]);
         }
     }
 }
@@ -824,7 +838,11 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
 // contiguous runs of the tile list, so one XCD works through compact
 // pieces of the same instances and finds their halos in its L2.
 template <typename S, typename R, int EOS, int DEV, bool SAVEF>
-__global__ __launch_bounds__(256) void k_main_batch(BatchArgs b) {
+// (three wavefronts per SIMD: the instance arguments add registers to the
+// tile's, and the benchmark's form would otherwise need one more than three
+// wavefronts leave)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_main_batch(
+    BatchArgs b) {
     if (!b.persistent) {
         batch_tile<S, R, EOS, DEV, SAVEF>(b, xcd_tile(blockIdx.x, gridDim.x));
         return;
