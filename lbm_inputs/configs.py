@@ -10,7 +10,8 @@ numbers below are inputs of the recipe, not results of the method:
   droplets; they are the coexistence densities of the plain pseudopotential
   model at those temperatures, rounded to six digits.
 * The virtual wall density defaults to the mean of the two, which gives a
-  contact angle near 90 degrees.
+  contact angle of about 79 degrees on a flat wall at 0.86 Tc, tau = 1
+  (measured with sessile droplets; 90 degrees needs about 0.130).
 """
 from __future__ import annotations
 
@@ -318,4 +319,25 @@ def cylinder_flow(re: float, fix: str = "A", d: float = 40.0, u0: float = 0.1,
                 rule=rule, fix=fix, ux0=np.where(fl, u0, 0.0), uy0=np.zeros((ny, nx)),
                 open_x=True, inlet_u=u0, name=f"cylinder_re{re:g}_d{d:g}")
     p.meta.update(owner=owner, cx=cx, cy=cy, d=d, u0=u0, re=re)
+    return p
+
+
+def sessile_droplet(rho_wall: float, nx: int = 200, ny: int = 100, floor: int = 4,
+                    r0: float = 30.0, t_over_tc: float = 0.86, tau: float = 1.0,
+                    rule: str = "mls", fix: str = "B", width: float = 4.0):
+    """A droplet on a flat floor (contact angle by a constant virtual wall
+    density, Sec. 3.2): a half disc of radius r0 centred on the wall, which
+    lies half-way between rows floor - 1 and floor (q = 1/2); periodic in x
+    and y (the floor is also the ceiling, far above the droplet); CS at
+    t_over_tc, BGK."""
+    rho_l, rho_v = cs_init_densities(t_over_tc)
+    yw = floor - 0.5
+    rho0 = geo.tanh_disc(nx, ny, 0.5 * nx, yw, r0, rho_l, rho_v, width)
+    # only the half above the floor: the other half would wrap to the top
+    rho0[ny // 2:] = rho_v
+    p = _problem(nx, ny, [geo.Band(0, floor)], rho0, rho_wall, eos="cs",
+                 eos_params=cs_params(t_over_tc), G=-1.0, collision="bgk", tau=tau,
+                 mrt_s=mrt_rates(tau), rule=rule, fix=fix,
+                 name=f"sessile_rw{rho_wall:g}")
+    p.meta.update(rho_l=rho_l, rho_v=rho_v, wall_y=yw, r0=r0)
     return p
