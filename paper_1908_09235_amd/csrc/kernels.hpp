@@ -513,17 +513,25 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
         if constexpr (DEV == 2) return double(A[q * P + n]) + wt(q) * double(rpl[n]);
         return DEV == 1 ? double(A[q * P + n]) + wt(q) * b.rref : double(A[q * P + n]);
     };
+    // the link's record, loaded beside its metadata (a padding slot of the
+    // table stands in for the lanes past its end): one round trip fewer
+    // before the populations
+    const int ic = i < b.nslot ? i : 0;
+    const int node_r = b.lnode[ic], slotb = b.lslotb[ic], slotf = b.lslotf[ic];
+    const int xf = b.lxf[ic], xff = b.lxff[ic];
+    double c[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) c[k] = b.lc[8 * ic + k];
+    const double uwx = b.luw[2 * ic], uwy = b.luw[2 * ic + 1];
     int node = 0;
     double fab = 0.0, r = 0.0, ch = 0.0, bk = 0.0, wl = 0.0;
     if (active) {
-        node = b.lnode[i];
+        node = node_r;
         const int od = opp(d);
-        const double* c = b.lc + 8 * i;
-        const double* mom = b.side_mom + 3 * b.lslotb[i];
+        const double* mom = b.side_mom + 3 * slotb;
         const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
         const double ex = double(cx(d)), ey = double(cy(d));
         fab = ld(d, node);
-        const double uwx = b.luw[2 * i], uwy = b.luw[2 * i + 1];
         // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
         wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
         if (kind == LK_HALFWAY) {
@@ -534,7 +542,7 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
                 usx = ubx;
                 usy = uby;
             } else if (kind == LK_CHI_UF) {
-                const double* mf = b.side_mom + 3 * b.lslotf[i];
+                const double* mf = b.side_mom + 3 * slotf;
                 usx = mf[1];
                 usy = mf[2];
             } else {
@@ -549,15 +557,15 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
             bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
             r = (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
         } else if (kind == LK_LIN_F) {
-            r = c[0] * fab + c[1] * ld(d, b.lxf[i]);
+            r = c[0] * fab + c[1] * ld(d, xf);
         } else if (kind == LK_LIN_B) {
             r = c[0] * fab + c[1] * ld(od, node);
         } else if (kind == LK_QUAD_F) {
-            r = c[0] * fab + c[1] * ld(d, b.lxf[i]) - c[2] * ld(d, b.lxff[i]);
+            r = c[0] * fab + c[1] * ld(d, xf) - c[2] * ld(d, xff);
         } else if (kind == LK_QUAD_B) {
-            r = c[0] * fab + c[1] * ld(od, node) - c[2] * ld(od, b.lxf[i]);
+            r = c[0] * fab + c[1] * ld(od, node) - c[2] * ld(od, xf);
         } else {  // LK_ZY, Eq. (14)
-            r = c[0] * ld(od, node) + c[1] * b.side_f[9 * b.lslotb[i] + d];
+            r = c[0] * ld(od, node) + c[1] * b.side_f[9 * slotb + d];
         }
     }
     s_fab[tid] = fab;
