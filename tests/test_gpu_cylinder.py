@@ -136,3 +136,22 @@ def test_table1_at_paper_resolution(L, re, fix):
     assert abs(got["wake"] / t1["2L/D"] - 1) <= 0.03
     assert min(thetas) - 0.5 <= got["theta"] <= max(thetas) + 0.5
     assert abs(got["Fy"]) <= 1e-6
+
+
+def test_checkpoint_resume_with_open_boundaries(L):
+    """A resumed run of the cylinder flow continues bit for bit, wall force
+    included; the force reads 0 until the first step after the restore."""
+    p = cfg.cylinder_flow(20.0, fix="B", d=8.0)
+    with L.Domain(p, storage="f64", history_capacity=512) as a:
+        a.step(41)
+        st = L.lbm_get_state(a.h)
+        a.step(23)
+        ra, fa, ha = a.moments(), a.wall_force(), a.mass_history()
+    with L.Domain(p, storage="f64", history_capacity=512) as b:
+        L.lbm_set_state(b.h, st)
+        assert b.t == 41 and np.array_equal(b.wall_force(), [0.0, 0.0])
+        b.step(23)
+        rb, fb, hb = b.moments(), b.wall_force(), b.mass_history()
+    for i in range(3):
+        assert np.array_equal(ra[i], rb[i])
+    assert np.array_equal(fa, fb) and np.array_equal(ha, hb)
