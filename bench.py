@@ -80,6 +80,24 @@ def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_every,
                 bnd_ms=bnd_ms / max(bnd_n, 1), samples=main_n, drift=drift, mom=mom)
 
 
+def copy_bandwidth(torch, mib=1024, reps=20):
+    """Read + write rate of a plain device copy of mib MiB (HIP events):
+    what this HBM delivers to the simplest streaming kernel."""
+    x = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return round(2 * (mib << 20) / (ms * 1e-3) / 1e9, 1)
+
+
 def precision_leg(steps, warmup, stream, prof_every):
     """Many cylinders with droplets, 8192 x 4096, CS at 0.86 Tc, BGK
     tau = 0.8, MLS + B: each storage form run from the same start for the
@@ -350,6 +368,7 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
+    copy_gbs = copy_bandwidth(torch)
     r = run_gpu(p, a.storage, a.steps, a.warmup, stream, a.tile_w, a.tile_h, a.prof_every)
     fluid = r["info"]["fluid_nodes"]
     s = BYTES_PER_POP[a.storage]
@@ -413,6 +432,7 @@ def main():
                      "kernel": "k_main", "kernel_ms": round(r["main_ms"], 5),
                      "kernel_samples": r["samples"],
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "copy_gbs": copy_gbs,
                      "boundary_kernel_ms": round(r["bnd_ms"], 5)},
         "cpu_baseline": cpu,
         "also": also,
