@@ -10,7 +10,10 @@ Prints one JSON line: MLUPS over fluid nodes (whole job) of the plain form
 with FP32 populations (FP64 arithmetic), the roofline of the main kernel
 (achieved HBM GB/s from its algorithmic bytes and its mean launch duration,
 timed with HIP events on its stream), the FP64-storage and FP32-arithmetic
-forms of the same workload, and the CPU oracle timed on a bounded sample.
+forms of the same workload, the precision forms on 8192 x 4096, the
+batched and served forms, the paper's other experiments (flow past a
+cylinder, gravity q-sweep, contact angle), and the CPU oracle timed on a
+bounded sample.
 """
 import argparse
 import hashlib
@@ -129,6 +132,88 @@ def precision_leg(steps, warmup, stream, prof_every):
                 rec[f"err_{nm}"] = float(np.max(np.abs(r["mom"][i][fl] - ref[i][fl])) / den)
         out[st] = rec
     out["fluid_nodes"] = fluid
+    return out
+
+
+def workloads_leg(stream, cyl_steps=40000, grav_steps=60000, ca_steps=30000):
+    """The paper's other experiments on the same library, timed (the run
+    only, not the set-up): flow past a cylinder (Sec. 4.2, Table 1; Re = 20,
+    scheme A, D = 40, FP64, a fixed number of steps), the static flow under
+    gravity over q (Sec. 3.1; 36 instances in one batch) and the contact
+    angle against the virtual wall density (ten sessile droplets in one
+    batch)."""
+    import numpy as np
+    import torch
+
+    from lbm_inputs import configs as cfg
+    from paper_1908_09235_amd import lbm
+    from paper_1908_09235_amd import observables as obs
+
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.json")) as f:
+        table1 = json.load(f)["table1"]["Re20"]["A"]
+    out = {}
+
+    p = cfg.cylinder_flow(20.0, fix="A")
+    m = p.meta
+    with lbm.Domain(p, storage="f64", stream=stream, history_capacity=1024) as d:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d.step(cyl_steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        F = d.wall_force()
+        rho, ux, uy = d.moments()
+    r = 0.5 * m["d"]
+    out["cylinder"] = {
+        "workload": f"cylinder_re20_A_{p.nx}x{p.ny}", "storage": "f64", "steps": cyl_steps,
+        "seconds": round(sec, 2), "mlups": round(p.fluid_nodes * cyl_steps / sec / 1e6, 1),
+        "Cd": round(float(obs.drag_coefficient(F[0], m["u0"], m["d"])), 4),
+        "2L/D": round(float(obs.wake_length(ux, m["cx"], m["cy"], r)), 3),
+        "theta_s": round(float(obs.separation_angle(ux, uy, p.solid, m["cx"], m["cy"], r)), 2),
+        "paper": table1}
+
+    rules = ("mls", "ibb_linear", "ibb_quadratic", "zhao_yong")
+    qs = tuple(n / 10 for n in range(1, 10))
+    probs = {(ru, q): cfg.static_gravity(q, rule=ru) for ru in rules for q in qs}
+    with lbm.Batch(storage="f64", eos="none", max_instances=len(probs), tile_w=128,
+                   tile_h=16, arena_bytes=1 << 28, graph_steps=32, stream=stream) as b:
+        slots = {k: b.add(pp, grav_steps, history_capacity=grav_steps + 1)
+                 for k, pp in probs.items()}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(grav_steps)
+        b.sync()
+        sec = time.perf_counter() - t0
+        eps = {}
+        for (ru, q), sl in slots.items():
+            h = b.mass_history(sl)
+            eps.setdefault(ru, {})[f"{q:.1f}"] = float(f"{100 * abs(h[-1] - h[0]) / h[0]:.4g}")
+    nodes = sum(pp.fluid_nodes for pp in probs.values())
+    out["gravity_q_sweep"] = {
+        "workload": "static_gravity_100x50_q0.1..0.9_x4rules", "storage": "f64",
+        "instances": len(probs), "steps": grav_steps, "seconds": round(sec, 2),
+        "mlups": round(nodes * grav_steps / sec / 1e6, 1), "eps_percent": eps}
+
+    rws = (0.10, 0.12, 0.13, 0.147, 0.18, 0.22)
+    probs = [cfg.sessile_droplet(rw, nx=400, ny=200, r0=60.0) for rw in rws]
+    with lbm.Batch(storage="f64", eos="cs", max_instances=len(probs), arena_bytes=1 << 30,
+                   graph_steps=32, stream=stream) as b:
+        slots = [b.add(pp, ca_steps, history_capacity=64) for pp in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(ca_steps)
+        b.sync()
+        sec = time.perf_counter() - t0
+        th = {}
+        for rw, pp, sl in zip(rws, probs, slots):
+            lvl = 0.5 * (pp.meta["rho_l"] + pp.meta["rho_v"])
+            th[f"{rw:g}"] = round(obs.contact_angle(b.moments(sl)[0], pp.solid, pp.meta["wall_y"],
+                                                    lvl, y_max=pp.ny - 3.5)[0], 2)
+    nodes = sum(pp.fluid_nodes for pp in probs)
+    out["contact_angle"] = {
+        "workload": "sessile_droplet_400x200_r60_cs0.86", "storage": "f64",
+        "instances": len(probs), "steps": ca_steps, "seconds": round(sec, 2),
+        "mlups": round(nodes * ca_steps / sec / 1e6, 1), "theta_deg_by_rho_wall": th}
     return out
 
 
@@ -340,6 +425,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="arrival window of each served run (0: skip)")
     ap.add_argument("--serve-chunk", type=int, default=100)
+    ap.add_argument("--workloads", type=int, default=1,
+                    help="also time the paper's other experiments (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter "
                          "calibration under rocprofv3)")
@@ -405,6 +492,8 @@ def main():
     if a.serve_seconds > 0:
         serve = serve_leg("f32", a.serve_seconds, [0.5, 0.8, 1.0], a.serve_chunk, 128)
 
+    other = workloads_leg(stream) if a.workloads else None
+
     cpu = None
     if a.cpu_seconds > 0:
         n, t = cpu_baseline(p, a.cpu_seconds)
@@ -439,6 +528,7 @@ def main():
         "precision": prec,
         "batched": batch,
         "served": serve,
+        "paper_experiments": other,
     }
     print(json.dumps(out), flush=True)
 

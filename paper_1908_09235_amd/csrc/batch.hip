@@ -75,7 +75,8 @@ struct lbm_batch {
     int* h_small = nullptr;  // qbound[9], nlblk
 
     hipGraphExec_t graph = nullptr;
-    int graph_key[5] = {0, 0, 0, 0, 0};  // tile_w, persistent, main grid, steps, save_f
+    // tile_w, persistent, main grid, steps, save_f, boundary grid, reduce grid
+    int graph_key[7] = {0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -273,11 +274,14 @@ BatchLaunch launch_of(lbm_batch* b) {
         const int occ = b->bd.storage == LBM_STORE_F64
                             ? batch_occupancy_f64(b->bd.eos, b->bd.storage, b->tile_w, L.save_f)
                             : batch_occupancy_f32(b->bd.eos, b->bd.storage, b->tile_w, L.save_f);
-        L.main_grid = b->ncu * std::max(occ, 1);
+        // no more workgroups than tiles: a small batch would otherwise pay
+        // for queue tickets of workgroups that find nothing to do
+        L.main_grid = (int)std::min<long long>((long long)b->ncu * std::max(occ, 1),
+                                               std::max<long long>(b->ntiles, 1));
     } else {
         L.main_grid = (int)std::max<long long>(b->ntiles, 1);
     }
-    L.bnd_grid = kBoundaryGrid;
+    L.bnd_grid = (int)std::min<long long>(kBoundaryGrid, std::max<long long>(b->nlblk, 1));
     L.red_grid = std::min<int>(kReduceGrid, std::max<int>((int)b->inst.size(), 1));
     L.stream = b->stream;
     return L;
@@ -301,7 +305,8 @@ int enqueue(lbm_batch* b, long long n) {
     const int G = b->graph_steps;
     long long done = 0;
     if (G > 0 && n >= G) {
-        const int key[5] = {b->tile_w, b->persistent, L.main_grid, G, L.save_f ? 1 : 0};
+        const int key[7] = {b->tile_w, b->persistent, L.main_grid, G, L.save_f ? 1 : 0,
+                            L.bnd_grid, L.red_grid};
         if (b->graph && std::memcmp(key, b->graph_key, sizeof key) != 0) drop_graph(b);
         if (!b->graph) {
             hipGraph_t g = nullptr;

@@ -12,7 +12,7 @@ import pytest
 
 from lbm_inputs import configs as cfg
 from oracle import core as ora
-from tests import _contact as ca
+from paper_1908_09235_amd import observables as ca
 
 
 def _cap_field(theta_deg, R=30.0, nx=200, ny=100, floor=4, lo=0.02, hi=0.27, w=4.0):

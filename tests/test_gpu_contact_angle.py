@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from lbm_inputs import configs as cfg
-from tests import _contact as ca
+from paper_1908_09235_amd import observables as ca
 
 pytestmark = pytest.mark.gpu
 

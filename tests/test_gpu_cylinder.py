@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from lbm_inputs import configs as cfg
-from tests import _cylinder as obs
+from paper_1908_09235_amd import observables as obs
 from tests._lib import rel_err
 
 pytestmark = pytest.mark.gpu
