@@ -294,6 +294,25 @@ def test_full_size_2048_matches_oracle(L, storage):
             MASS_TOL if storage == "f64" else 1e-7)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_full_size_8192_matches_oracle(L, storage):
+    """The 8192 x 4096 many-cylinder workload (96 cylinders with droplets,
+    BGK, MLS + B) against the oracle over its whole field for 2 steps
+    (33.5 M nodes; about 15 s of oracle time)."""
+    p = cfg.many_cylinders()
+    steps = 2
+    key = ("full8192", steps)
+    if key not in _ORACLE:
+        o = ora.Oracle(p)
+        m0 = o.total_mass()
+        hist = o.step(steps)
+        _ORACLE[key] = (*o.moments(), np.concatenate([[m0], hist]))
+    ref = _ORACLE[key]
+    g = gpu_run(L, p, steps, storage)
+    compare(p, g, ref, F64_TOL if storage == "f64" else F32_TOL,
+            MASS_TOL if storage == "f64" else 1e-7)
+
+
 def _couette_error(p, ux, uy):
     m = p.meta
     Y, X = np.mgrid[0:p.ny, 0:p.nx].astype(float)
