@@ -195,6 +195,23 @@ def test_full_batch_512_sampled(L):
             t, rem, u = b.status(slots[k])
             assert rem == 0
             assert same(b.moments(slots[k]), alone(L, probs[k], 60 if u < 0 else u, "f32")[0])
+        # and straight against the oracle (FP32 storage: the 1e-5 gate)
+        from oracle import core as ora
+        from tests._lib import rel_err
+        compared = 0
+        for k in (0, 17, 255, 511):
+            if b.status(slots[k])[2] >= 0:
+                continue
+            compared += 1
+            o = ora.Oracle(probs[k])
+            o.step(60)
+            ref = o.moments()
+            g = b.moments(slots[k])
+            fl = ~probs[k].solid.astype(bool)
+            e = [rel_err(g[i], ref[i], fl) for i in range(3)]
+            say(f"    instance {k} vs oracle: {e}")
+            assert max(e) <= 1e-5
+        assert compared >= 2
 
 
 def test_server_result_same_alone_and_in_mix(L):
