@@ -121,7 +121,8 @@ struct RowLoad {
     S f[9];
     uint8_t fl;
     int si;        // side slot (boundary nodes)
-    float rr[NR];  // densities of the nine source nodes (DEV 2)
+    float dr[NR];  // DEV 2: density two rows ahead, own column and edge column
+    float rr[9];   // DEV 2: densities of the nine source nodes
     float pw;      // FP16 storage: psi_w of a solid node in FP32
 };
 
@@ -153,7 +154,12 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     __shared__ R ring[4][kMaxTileW];
     __shared__ double wsum[kMaxTileW / 64];
     constexpr unsigned ES = sizeof(S);
-    constexpr int NR = DEV == 2 ? 9 : 1;
+    // DEV 2: the density plane's rows -2 .. H + 1 of the strip, with one
+    // column more on either side, pass through an LDS ring of eight rows:
+    // row j is loaded with row j - 2's populations, written at row j - 3's
+    // step and read by the decodes of rows j - 1 .. j + 1
+    constexpr int NR = DEV == 2 ? 2 : 1;
+    __shared__ float dring[DEV == 2 ? 8 : 1][kMaxTileW + 2];
     const unsigned pitch = (unsigned)a.pitch;
     // one resource per buffer; plane and row offsets go in the scalar
     // offset (the whole buffer is below 4 GiB)
@@ -203,6 +209,42 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     auto load_flags = [&](int k) {
         nfl = bload<uint8_t>(rfl, x, (unsigned)row_of(k) * pitch);
     };
+    // DEV 2: density row j of the ring (-2 <= j <= H + 1), own column, and
+    // for lanes 0 and ncols + 1 the column beyond
+    auto load_dens = [&](int j, RowLoad<S, R, NR>& L) {
+        const bool in = j >= -2 && j <= H + 1;
+        const unsigned q = rbase + (unsigned)(in ? row_of(j) : 0) * pitch * 4u;
+        L.dr[0] = bload<float>(rs, (in && act) ? x * 4u : kOOB, q);
+        const unsigned xe = tid == 0 ? xm : xp;
+        L.dr[1 % NR] = bload<float>(rs, (in && (tid == 0 || tid == ncols + 1)) ? xe * 4u : kOOB, q);
+    };
+    auto put_dens = [&](int j, const RowLoad<S, R, NR>& L) {
+        // lane t's column sits at t + 1; idle lanes write nothing
+        float* const d = dring[j & 7];
+        if (act) d[tid + 1] = L.dr[0];
+        if (tid == 0) d[0] = L.dr[1 % NR];
+        if (tid == ncols + 1) d[ncols + 3] = L.dr[1 % NR];
+    };
+    // DEV 2: densities of the nine nodes row k pulls from (0 where the node
+    // itself is not fluid); x - e_q lies in column tid + 1 - e_qx of the
+    // ring and in row k - e_qy * dir
+    auto src_dens = [&](int k, uint8_t fl, float rr[9]) {
+        const bool fluid = !(fl & FL_SOLID);
+        const float* const dm = dring[(k - dir) & 7];
+        const float* const d0 = dring[k & 7];
+        const float* const dp = dring[(k + dir) & 7];
+        rr[0] = d0[tid + 1];
+        rr[1] = d0[tid];
+        rr[2] = dm[tid + 1];
+        rr[3] = d0[tid + 2];
+        rr[4] = dp[tid + 1];
+        rr[5] = dm[tid];
+        rr[6] = dm[tid + 2];
+        rr[7] = dp[tid + 2];
+        rr[8] = dp[tid];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rr[q] = fluid ? rr[q] : 0.0f;
+    };
     // rows -1 .. H are pulled (the outer two for psi only); later ones only
     // keep the pipeline uniform and move nothing
     auto issue = [&](int k, RowLoad<S, R, NR>& L) {
@@ -227,22 +269,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         L.f[6] = bload<S>(rs, vp, 6 * pb + rm);
         L.f[7] = bload<S>(rs, vp, 7 * pb + rp);
         L.f[8] = bload<S>(rs, vm, 8 * pb + rp);
-        if constexpr (DEV == 2) {
-            // the source nodes' densities, rows of the FP32 plane
-            const unsigned qm = rbase + rm / ES * 4u, q0 = rbase + r0 / ES * 4u,
-                           qp = rbase + rp / ES * 4u;
-            const unsigned wc = fluid ? x * 4u : kOOB, wm = fluid ? xm * 4u : kOOB,
-                           wp = fluid ? xp * 4u : kOOB;
-            L.rr[0] = bload<float>(rs, wc, q0);
-            L.rr[1 % NR] = bload<float>(rs, wm, q0);
-            L.rr[2 % NR] = bload<float>(rs, wc, qm);
-            L.rr[3 % NR] = bload<float>(rs, wp, q0);
-            L.rr[4 % NR] = bload<float>(rs, wc, qp);
-            L.rr[5 % NR] = bload<float>(rs, wm, qm);
-            L.rr[6 % NR] = bload<float>(rs, wp, qm);
-            L.rr[7 % NR] = bload<float>(rs, wp, qp);
-            L.rr[8 % NR] = bload<float>(rs, wm, qp);
-        }
+        if constexpr (DEV == 2) load_dens(k + 2, L);
         if constexpr (ES == 2)
             L.pw = bload<float>(rpw, (own && !fluid) ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
         if constexpr (!MOMENTS) {
@@ -254,15 +281,20 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
                 L.si = bload<int>(rsi, side ? x * 4u : kOOB, (unsigned)y * pitch * 4u);
         }
     };
-    // stored form -> populations (DEV 2) or the stored form itself
-    auto decode = [&](const RowLoad<S, R, NR>& L, R f[9]) {
+    // stored form -> populations (DEV 2, with the source densities rr) or
+    // the stored form itself
+    auto decode = [&](const RowLoad<S, R, NR>& L, const float rr[9], R f[9]) {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            f[q] = DEV == 2 ? R(L.f[q]) + R(wt(q)) * R(L.rr[q % NR]) : R(L.f[q]);
+            f[q] = DEV == 2 ? R(L.f[q]) + R(wt(q)) * R(rr[q]) : R(L.f[q]);
     };
-    auto publish = [&](const RowLoad<S, R, NR>& L, int slot) {
+    // psi of row k into ring slot (k + 1) & 3 (DEV 2: with the source
+    // densities of the row, kept for its collision)
+    auto publish = [&](RowLoad<S, R, NR>& L, int k) {
+        const int slot = (k + 1) & 3;
+        if constexpr (DEV == 2) src_dens(k, L.fl, L.rr);
         R f[9];
-        decode(L, f);
+        decode(L, L.rr, f);
         const R rho = DEV == 1 ? ph.rref + dens<R>(f) : dens<R>(f);
         const R pw = ES == 2 ? R(L.pw) : R(L.f[0]);
         ring[slot][tid] = (L.fl & FL_SOLID) ? pw : psi_of<EOS, R>(rho, ph);
@@ -274,11 +306,13 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         const int y = row_of(k);
         const int sm = k & 3, s0 = (k + 1) & 3, sp = (k + 2) & 3;
         const int sym = dir > 0 ? sm : sp, syp = dir > 0 ? sp : sm;
-        publish(Ln, sp);
+        if constexpr (DEV == 2) put_dens(k + 3, Ln);
+        publish(Ln, k + 1);
         __syncthreads();
         const bool live = upd && k < H && !(Lc.fl & FL_SOLID);
+        const float* const rr = Lc.rr;
         R fc[9];  // f, or (DEV 1) the deviations g
-        decode(Lc, fc);
+        decode(Lc, rr, fc);
         const int c = tid;
         const R drho = dens<R>(fc);
         const R rho = DEV == 1 ? ph.rref + drho : drho;
@@ -321,7 +355,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             if constexpr (DEV == 2) {
                 rho_d = 0.0;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) rho_d += double(Lc.f[q]) + wt(q) * double(Lc.rr[q % NR]);
+                for (int q = 0; q < 9; ++q) rho_d += double(Lc.f[q]) + wt(q) * double(rr[q]);
             }
             msum += live ? rho_d : 0.0;
             // moments of boundary nodes (and pre-collision populations)
@@ -353,7 +387,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             for (int q = 0; q < 9; ++q) {
                 // DEV 2: re-encoded against this node's density,
                 // g* = g + w (r(x - e) - rho) + dh, without forming f
-                const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(Lc.rr[q % NR]) - rho)) + dh[q]
+                const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(rr[q]) - rho)) + dh[q]
                                      : fc[q] + dh[q];
                 bstore(S(v), rd, vo, q * pb + r0);
             }
@@ -364,13 +398,28 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
     };
 
     RowLoad<S, R, NR> A, B, C;
+    // DEV 2: density rows -2 .. 0 here, 1 and 2 with the first two issues
+    RowLoad<S, R, NR> D0, D1, D2;
+    if constexpr (DEV == 2) {
+        load_dens(-2, D0);
+        load_dens(-1, D1);
+        load_dens(0, D2);
+    }
     load_flags(-1);
     issue(-1, C);
     issue(0, A);
     issue(1, B);
-    publish(C, 0);
+    if constexpr (DEV == 2) {
+        put_dens(-2, D0);
+        put_dens(-1, D1);
+        put_dens(0, D2);
+        put_dens(1, C);
+        put_dens(2, A);
+        __syncthreads();
+    }
+    publish(C, -1);
     issue(2, C);
-    publish(A, 1);
+    publish(A, 0);
     // a whole number of three-row rotations; rows k >= H store nothing
     const int H3 = (H + 2) / 3 * 3;
     for (int k = 0; k < H3; k += 3) {
