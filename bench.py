@@ -13,7 +13,8 @@ timed with HIP events on its stream), the FP64-storage and FP32-arithmetic
 forms of the same workload, the precision forms on 8192 x 4096, the
 batched and served forms, the paper's other experiments (flow past a
 cylinder, gravity q-sweep, contact angle), and the CPU oracle timed on a
-bounded sample.
+bounded sample (one copy, then one independent copy per usable core at
+once, before the GPU is touched).
 """
 import argparse
 import hashlib
@@ -28,8 +29,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_POP = {"f64": 8, "f32": 4, "f32_arith32": 4, "f32dev": 4, "f16dev": 2, "f16node": 2}
 # algorithmic bytes per lattice update beyond the 18 populations (the
-# per-node reference read of the FP16 per-node form)
-EXTRA_BYTES = {"f16node": 4}
+# FP16 per-node form reads and writes each node's FP32 density)
+EXTRA_BYTES = {"f16node": 8}
 ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32", "f32dev": "f32", "f16dev": "f32",
          "f16node": "f32"}
 
@@ -400,6 +401,54 @@ def cpu_baseline(p, seconds):
     return n, t
 
 
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_leg(scale, seconds, procs):
+    """The oracle on the benchmark's workload: one copy in this process,
+    then `procs` independent copies at once in child processes (the
+    oracle is single-threaded; their summed rate is what the host's cores
+    give).  Runs before anything touches the GPU."""
+    import subprocess
+
+    from lbm_inputs import configs as cfg
+
+    p = cfg.cfg2a(scale=scale)
+    fluid = int((~p.solid.astype(bool)).sum())
+    n, t = cpu_baseline(p, seconds)
+    del p
+    out = {"value": round(fluid * n / t / 1e6, 3), "unit": "MLUPS", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{n} steps of the same workload (FP64 C oracle, single thread, "
+                     f"{t:.1f} s)",
+           "host": host_cpu()}
+    if procs > 1:
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker",
+               str(seconds), "--scale", str(scale)]
+        kids = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
+        res = []
+        for k in kids:
+            o, _ = k.communicate()
+            if k.returncode != 0:
+                raise RuntimeError(f"oracle worker failed ({k.returncode})")
+            res.append(json.loads(o.strip().splitlines()[-1]))
+        rate = sum(fluid * r["n"] / r["t"] for r in res)
+        out["all_cores"] = {"value": round(rate / 1e6, 3), "unit": "MLUPS", "procs": procs,
+                            "sample": f"{procs} independent copies at once, "
+                                      f"{sum(r['n'] for r in res)} steps in all"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,6 +466,10 @@ def main():
                          "(events between the launches of every step would "
                          "add their own cost to the timed steps)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle copies run at once for the all-cores rate "
+                         "(0: the usable cores, at most 16; 1: skip)")
+    ap.add_argument("--oracle-worker", type=float, default=0.0, help=argparse.SUPPRESS)
     ap.add_argument("--precision-steps", type=int, default=2000,
                     help="steps of the 8192 x 4096 precision-form comparison (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5000,
@@ -432,10 +485,24 @@ def main():
                          "calibration under rocprofv3)")
     a = ap.parse_args()
 
+    if a.oracle_worker > 0:
+        # a child of the CPU leg: time one oracle copy, print (steps, seconds)
+        from lbm_inputs import configs as cfg
+
+        n, t = cpu_baseline(cfg.cfg2a(scale=a.scale), a.oracle_worker)
+        print(json.dumps({"n": n, "t": t}), flush=True)
+        return
+
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the domain is not "
               "sharded); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU leg first, before anything touches the GPU
+    cpu = None
+    if a.cpu_seconds > 0:
+        procs = a.cpu_procs or min(len(os.sched_getaffinity(0)), 16)
+        cpu = cpu_leg(a.scale, a.cpu_seconds, procs)
 
     import torch
 
@@ -494,13 +561,6 @@ def main():
 
     other = workloads_leg(stream) if a.workloads else None
 
-    cpu = None
-    if a.cpu_seconds > 0:
-        n, t = cpu_baseline(p, a.cpu_seconds)
-        cpu = {"value": round(fluid * n / t / 1e6, 3), "unit": "MLUPS", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{n} steps of the same {p.nx}x{p.ny} workload (FP64 C oracle, "
-                         f"single thread, {t:.1f} s)"}
 
     out = {
         "metric": "MLUPS (fluid-node lattice updates per second), plain step",
