@@ -282,11 +282,13 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         }
     };
     // stored form -> populations (DEV 2, with the source densities rr) or
-    // the stored form itself
+    // the stored form itself.  DEV 2 fuses the multiply-add explicitly: the
+    // row loop's unrolled copies must round alike whatever the compiler
+    // would contract in each
     auto decode = [&](const RowLoad<S, R, NR>& L, const float rr[9], R f[9]) {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            f[q] = DEV == 2 ? R(L.f[q]) + R(wt(q)) * R(rr[q]) : R(L.f[q]);
+            f[q] = DEV == 2 ? fma(R(wt(q)), R(rr[q]), R(L.f[q])) : R(L.f[q]);
     };
     // psi of row k into ring slot (k + 1) & 3 (DEV 2: with the source
     // densities of the row, kept for its collision)
@@ -387,7 +389,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             for (int q = 0; q < 9; ++q) {
                 // DEV 2: re-encoded against this node's density,
                 // g* = g + w (r(x - e) - rho) + dh, without forming f
-                const R v = DEV == 2 ? (R(Lc.f[q]) + R(wt(q)) * (R(rr[q]) - rho)) + dh[q]
+                const R v = DEV == 2 ? fma(R(wt(q)), R(rr[q]) - rho, R(Lc.f[q])) + dh[q]
                                      : fc[q] + dh[q];
                 bstore(S(v), rd, vo, q * pb + r0);
             }

@@ -175,14 +175,38 @@ def test_ragged_tiles_parity(L, tw, th):
             F64_TOL, MASS_TOL)
 
 
-def test_results_do_not_depend_on_tiling(L):
-    """rho and u are bit-identical for every launch shape."""
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32_arith32", "f32dev", "f16dev", "f16node"])
+def test_results_do_not_depend_on_tiling(L, storage):
+    """rho and u are bit-identical for every launch shape (a row lands in
+    a different unrolled copy of the row loop at each tile height)."""
     p = cfg.cfg1("mls", "B")
-    ref = gpu_run(L, p, 200, tile_w=128, tile_h=16)
-    for tw, th in [(64, 16), (64, 5), (128, 128), (256, 3)]:
-        g = gpu_run(L, p, 200, tile_w=tw, tile_h=th)
+    ref = gpu_run(L, p, 200, storage=storage, tile_w=128, tile_h=16)
+    for tw, th in [(64, 16), (64, 5), (128, 128), (256, 3), (64, 1)]:
+        g = gpu_run(L, p, 200, storage=storage, tile_w=tw, tile_h=th)
         for i in range(3):
             assert np.array_equal(g[i], ref[i]), (tw, th, i)
+
+
+# FP16 per-node storage against the oracle: (rho, u) bounds, as for the
+# deviation forms
+F16NODE_TOL = (1e-3, 1e-2)
+
+
+def test_ragged_tiles_fp16_per_node(L):
+    """The FP16 per-node form on the 67 x 53 case: the same fields at every
+    ragged launch shape (strip tails of 3 columns, one-row segments), and
+    within its bounds of the oracle."""
+    p = _ragged_problem()
+    runs = [gpu_run(L, p, 300, storage="f16node", tile_w=tw, tile_h=th)
+            for tw, th in [(64, 16), (128, 7), (256, 53), (64, 1)]]
+    for g in runs[1:]:
+        for i in range(3):
+            assert np.array_equal(g[i], runs[0][i])
+    o = oracle_run(p, 300)
+    fl = ~p.solid.astype(bool)
+    e = [rel_err(runs[0][i], o[i], fl) for i in range(3)]
+    say(f"    rel err rho {e[0]:.3e} ux {e[1]:.3e} uy {e[2]:.3e}")
+    assert e[0] <= F16NODE_TOL[0] and max(e[1:]) <= F16NODE_TOL[1]
 
 
 def test_tiny_domain_without_walls(L):
@@ -194,6 +218,13 @@ def test_tiny_domain_without_walls(L):
     rho0 = 0.1 + 0.02 * rng.random((n, n))
     p = cfg.free_droplet(n, 1.0).with_(rho0=rho0, name="tiny3")
     compare(p, gpu_run(L, p, 2), oracle_run(p, 2), F64_TOL, MASS_TOL)
+    # FP16 per-node storage: every density the decode reads wraps too
+    g = gpu_run(L, p, 2, storage="f16node")
+    fl = ~p.solid.astype(bool)
+    o = oracle_run(p, 2)
+    e = [rel_err(g[i], o[i], fl) for i in range(3)]
+    say(f"    f16node rel err rho {e[0]:.3e} ux {e[1]:.3e} uy {e[2]:.3e}")
+    assert e[0] <= F16NODE_TOL[0] and max(e[1:]) <= F16NODE_TOL[1]
 
 
 @pytest.mark.parametrize("storage,rule", [("f64", "mls"), ("f32", "mls"), ("f16node", "mls"),
