@@ -115,9 +115,13 @@ typedef struct {
 
 typedef struct {
     int32_t nx, ny;            /* lattice size, each >= 3, nx*ny < 2^30;
-                                  one buffer of nine planes must stay below
-                                  4 GiB (about 59 M nodes in FP64, 119 M in
-                                  FP32)                                   */
+                                  one state buffer must stay below
+                                  2^32 - 256 bytes: nine planes of
+                                  pitch*ny + 256 elements (pitch = nx
+                                  rounded up to 64), plus an FP32 plane of
+                                  that size for the FP16 per-node form
+                                  (about 59 M nodes in FP64, 119 M in
+                                  FP32, 195 M FP16 per-node)            */
     const uint8_t *solid;      /* host, nx*ny, nonzero = solid node         */
     const lbm_link *links;     /* host, nlinks cut links                    */
     int64_t nlinks;

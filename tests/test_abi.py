@@ -196,3 +196,19 @@ def test_batch_descriptors_are_validated(L):
                      ("lbm_server_progress", (None, None, 0, None)),
                      ("lbm_server_release", (None, 0)), ("lbm_server_info", (None, None))):
         assert getattr(lib, fn)(*args) == L.LBM_EINVAL, fn
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "f16node"])
+def test_state_buffer_limit_is_enforced_at_create(L, storage):
+    """One row past the largest domain whose state buffer fits in 32-bit
+    offsets is rejected before any array is read (so a small problem's
+    arrays can stand in); so is nx * ny >= 2^30."""
+    from tests._limits import max_rows
+    p = cfg.cfg1()
+    d, keep = L.make_desc(p, storage=storage)
+    h = ctypes.c_void_p()
+    nx = 16384
+    d.nx, d.ny = nx, max_rows(storage, nx) + 1
+    assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
+    d.nx, d.ny = 1 << 15, 1 << 15
+    assert L.lib().lbm_create_domain(ctypes.byref(d), ctypes.byref(h)) == L.LBM_EINVAL
