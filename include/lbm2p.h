@@ -292,7 +292,8 @@ int lbm_batch_remove(lbm_batch *b, int32_t slot);
  * warm-up step) under each main-pass shape (tile_w 64/128/256, tile_h
  * 8/16/32, persistent or not), keeps the fastest and reports it in out:
  * tile_w, tile_h, persistent, microseconds per step.  The steps count as
- * steps of the instances; results do not depend on the shape. */
+ * steps of the instances; results do not depend on the shape.  A batch
+ * with no instances keeps its shape and reports 0 microseconds. */
 int lbm_batch_tune(lbm_batch *b, int64_t steps_per_trial, int32_t out[4]);
 
 /* [0] instances, [1] main-pass tiles, [2] link blocks, [3] arena bytes,

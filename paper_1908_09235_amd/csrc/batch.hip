@@ -533,6 +533,15 @@ int lbm_batch_tune(lbm_batch* b, int64_t steps_per_trial, int32_t out[4]) {
     if (!b || steps_per_trial < 1 || !out) return LBM_EINVAL;
     int rc = sync_batch(b);
     if (rc) return rc;
+    if (b->dirty && (rc = rebuild(b))) return rc;
+    if (b->ntiles == 0) {
+        // nothing to time: the shape stays as it is
+        out[0] = b->tile_w;
+        out[1] = b->tile_h;
+        out[2] = b->persistent;
+        out[3] = 0;
+        return LBM_OK;
+    }
     const int tws[3] = {64, 128, 256}, ths[3] = {8, 16, 32};
     float best = -1.0f;
     int bw = b->tile_w, bh = b->tile_h, bp = b->persistent;
@@ -550,6 +559,9 @@ int lbm_batch_tune(lbm_batch* b, int64_t steps_per_trial, int32_t out[4]) {
                 if (!rc) rc = enqueue(b, steps_per_trial);
                 if (!rc && hipEventRecord(b->ev1, b->stream) != hipSuccess) rc = LBM_EDEVICE;
                 if (!rc) rc = sync_batch(b);
+                // (the stop event is waited for on its own: a run that
+                // launched nothing leaves no batch work to wait for)
+                if (!rc && hipEventSynchronize(b->ev1) != hipSuccess) rc = LBM_EDEVICE;
                 float ms = 0.0f;
                 if (!rc && hipEventElapsedTime(&ms, b->ev0, b->ev1) != hipSuccess) rc = LBM_EDEVICE;
                 if (rc) break;
