@@ -316,8 +316,8 @@ typedef struct lbm_server lbm_server;
 
 int lbm_server_create(const lbm_batch_desc *bd, int64_t chunk_steps, lbm_server **out);
 int lbm_server_submit(lbm_server *s, const lbm_desc *desc, int64_t steps, int64_t *id);
-/* done_ids receives the ids that finished in this round (at most cap;
- * LBM_EINVAL if more finished, all still reported by *n_done = cap). */
+/* done_ids receives the ids of finished requests not reported before, at
+ * most cap of them (*n_done); any others are reported by later calls. */
 int lbm_server_progress(lbm_server *s, int64_t *done_ids, int64_t cap, int64_t *n_done);
 /* A finished request: its final rho, u (host arrays of nx*ny, any may be
  * NULL), mass[0] = M(0) (NaN if it left the history ring) and mass[1] =

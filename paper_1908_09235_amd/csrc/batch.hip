@@ -642,13 +642,14 @@ int lbm_server_progress(lbm_server* s, int64_t* done_ids, int64_t cap, int64_t* 
     // 1. the chunk in flight
     int rc = sync_batch(b);
     if (rc) return rc;
+    // finished requests are reported at most cap at a time; the others stay
+    // unreported (they run no more steps) for the next calls
     long long nd = 0;
-    for (int i = 0; i < (int)b->inst.size(); ++i) {
+    for (int i = 0; i < (int)b->inst.size() && nd < cap; ++i) {
         if (!b->inst[i] || s->finished[i] || !b->joined[i]) continue;
         if (b->state[i].remaining <= 0) {
             s->finished[i] = 1;
-            if (nd < cap) done_ids[nd] = s->id_of[i];
-            ++nd;
+            done_ids[nd++] = s->id_of[i];
         }
     }
     // 2. the next chunk for everything resident
@@ -681,8 +682,8 @@ int lbm_server_progress(lbm_server* s, int64_t* done_ids, int64_t cap, int64_t* 
         ++s->admitted;
         s->queue.pop_front();
     }
-    *n_done = std::min<long long>(nd, cap);
-    return nd > cap ? LBM_EINVAL : LBM_OK;
+    *n_done = nd;
+    return LBM_OK;
 }
 
 int lbm_server_result(lbm_server* s, int64_t id, double* rho, double* ux, double* uy,

@@ -557,8 +557,8 @@ class Server:
         self.shape[rid] = (problem.nx, problem.ny)
         return rid
 
-    def progress(self):
-        done = lbm_server_progress(self.h)
+    def progress(self, cap=4096):
+        done = lbm_server_progress(self.h, cap)
         # requests leave the queue in id order: the first admitted + rejected
         # ids no longer need their arrays
         info = self.info()

@@ -263,3 +263,27 @@ def test_server_rejects_what_never_fits(L):
         info = srv.info()
         assert rs in got and rb not in got
         assert info["rejected"] == 1 and info["queued"] == 0
+
+
+def test_server_reports_finished_requests_cap_at_a_time(L):
+    """Three requests finish in the same round; with room for one id per
+    call each is reported exactly once, over three calls, and none is lost."""
+    probs = small_mix(3, 64, 96, seed=7)
+    say("[gpu] server: three requests finish together, progress cap 1")
+    with L.Server(chunk_steps=16, storage="f32", eos="cs", max_instances=4,
+                  arena_bytes=64 << 20) as srv:
+        ids = [srv.submit(p, 10, history_capacity=64) for p in probs]
+        seen, calls = [], 0
+        while len(seen) < 3:
+            calls += 1
+            assert calls < 20
+            got = srv.progress(cap=1)
+            assert len(got) <= 1
+            seen += got
+        assert sorted(seen) == sorted(ids)
+        assert srv.progress(cap=1) == []
+        for rid in ids:
+            assert srv.result(rid, fields=False)["steps"] == 10
+            srv.release(rid)
+        info = srv.info()
+        assert info["finished"] == 0 and info["running"] == 0 and info["arena_used"] == 0
