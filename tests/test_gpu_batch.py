@@ -5,6 +5,7 @@ alone, with the same main-pass tile shape: rho, u and the mass history must
 agree bit for bit.  The FP32 batch is also held to 1e-5 of the FP64 form
 (the gate of the batched workload), and the served form must give each
 request the result it gets alone, whatever else is in the mix."""
+import ctypes
 import sys
 
 import numpy as np
@@ -287,3 +288,21 @@ def test_server_reports_finished_requests_cap_at_a_time(L):
             srv.release(rid)
         info = srv.info()
         assert info["finished"] == 0 and info["running"] == 0 and info["arena_used"] == 0
+
+
+def test_batch_refuses_instances_of_another_form(L):
+    """An instance must have the batch's storage form and EOS: its kernels
+    read every instance's buffers in the batch's element size."""
+    p = cfg.cfg1("mls", "B")  # CS EOS
+    single = cfg.static_gravity(0.3)  # no EOS
+    say("[gpu] batch refuses instances of another storage form or EOS")
+    with L.Batch(storage="f32", eos="cs", max_instances=4, arena_bytes=1 << 28) as b:
+        for prob, st in ((p, "f64"), (p, "f16node"), (single, "f32")):
+            d, keep = L.make_desc(prob, storage=st)
+            slot = ctypes.c_int32(-1)
+            assert L.lib().lbm_batch_add(b.h, ctypes.byref(d), 10, ctypes.byref(slot)) == L.LBM_EINVAL
+        assert b.info()["instances"] == 0
+        s = b.add(p, 3)
+        b.run(3)
+        b.sync()
+        assert b.status(s)[0] == 3
