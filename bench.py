@@ -433,19 +433,30 @@ def cpu_leg(scale, seconds, procs):
                      f"{t:.1f} s)",
            "host": host_cpu()}
     if procs > 1:
+        # a secondary figure: a failed or late copy is reported, not fatal
         cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker",
                str(seconds), "--scale", str(scale)]
         kids = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
-        res = []
+        res, err = [], None
         for k in kids:
-            o, _ = k.communicate()
+            try:
+                o, _ = k.communicate(timeout=seconds + 120)
+            except subprocess.TimeoutExpired:
+                k.kill()
+                k.communicate()
+                err = "an oracle copy did not finish in time"
+                continue
             if k.returncode != 0:
-                raise RuntimeError(f"oracle worker failed ({k.returncode})")
+                err = f"an oracle copy failed ({k.returncode})"
+                continue
             res.append(json.loads(o.strip().splitlines()[-1]))
-        rate = sum(fluid * r["n"] / r["t"] for r in res)
-        out["all_cores"] = {"value": round(rate / 1e6, 3), "unit": "MLUPS", "procs": procs,
-                            "sample": f"{procs} independent copies at once, "
-                                      f"{sum(r['n'] for r in res)} steps in all"}
+        if err is None:
+            rate = sum(fluid * r["n"] / r["t"] for r in res)
+            out["all_cores"] = {"value": round(rate / 1e6, 3), "unit": "MLUPS", "procs": procs,
+                                "sample": f"{procs} independent copies at once, "
+                                          f"{sum(r['n'] for r in res)} steps in all"}
+        else:
+            out["all_cores"] = {"value": None, "procs": procs, "error": err}
     return out
 
 
