@@ -1,0 +1,73 @@
+"""Randomized parity sweep: seeded small problems that mix lattice size,
+discs (some rotating) and a flat wall with arbitrary wall fractions, every
+rule and the fixes it admits, no EOS / exponential / Carnahan-Starling with
+a droplet, BGK or MRT, a body force, and the launch shape, against the
+oracle in FP64 after 60 steps (or at the same first unstable step)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core as ora
+from tests._lib import rel_err
+from tests._random_cases import random_case
+from tests.test_random_cases import N_CASES, STEPS
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+MASS_TOL = 1e-13
+# velocities are compared relative to max(max|u|, U_FLOOR): a case near rest
+# (gravity ~1e-5, 2 % density noise) has max|u| ~ 1e-4, where the rounding
+# of O(0.1) populations alone is ~1e-16 absolute per step
+U_FLOOR = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_09235_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
+def test_random_case_matches_oracle(L, k):
+    p, tile_w, tile_h = random_case(k)
+    say(f"[gpu] random case {k}: {p.nx}x{p.ny} {p.rule}/{p.fix} eos={p.eos} "
+        f"{p.collision} tau={p.tau:.3f} g={p.gravity} tiles {tile_w}x{tile_h}")
+    o = ora.Oracle(p)
+    m0 = o.total_mass()
+    try:
+        hist = o.step(STEPS)
+        bad = None
+    except ora.OracleError:
+        bad = o.t
+    with L.Domain(p, storage="f64", tile_w=tile_w, tile_h=tile_h, history_capacity=256) as d:
+        if bad is not None:
+            with pytest.raises(L.LbmError) as e:
+                d.step(STEPS)
+            assert e.value.code == L.LBM_EUNSTABLE
+            assert L.lbm_unstable_step(d.h) == bad
+            say(f"    both unstable at step {bad}")
+            return
+        d.step(STEPS)
+        got = d.moments()
+        gh = d.mass_history()
+    ref = o.moments()
+    fl = ~p.solid.astype(bool)
+    umax = max(np.max(np.abs(ref[1][fl])), np.max(np.abs(ref[2][fl])))
+    scale = max(umax, U_FLOOR)
+    e = [rel_err(got[0], ref[0], fl)] + \
+        [float(np.max(np.abs(got[i][fl] - ref[i][fl]))) / scale for i in (1, 2)]
+    oh = np.concatenate([[m0], hist])
+    dm = float(np.max(np.abs(gh - oh) / np.abs(oh)))
+    say(f"    rel err rho {e[0]:.2e} ux {e[1]:.2e} uy {e[2]:.2e} (max|u| {umax:.1e}) "
+        f"mass {dm:.2e}")
+    assert max(e) <= F64_TOL
+    assert np.all(got[0][~fl] == 0)
+    assert gh.size == STEPS + 1 and dm <= MASS_TOL
