@@ -2,7 +2,8 @@
 discs (some rotating) and a flat wall with arbitrary wall fractions, every
 rule and the fixes it admits, no EOS / exponential / Carnahan-Starling with
 a droplet, BGK or MRT, a body force, and the launch shape, against the
-oracle in FP64 after 60 steps (or at the same first unstable step)."""
+oracle after 60 steps (or at the first unstable step): FP64 storage
+within 1e-12, FP32 storage (FP64 arithmetic) within 1e-5."""
 import sys
 
 import numpy as np
@@ -15,12 +16,13 @@ from tests.test_random_cases import N_CASES, STEPS
 
 pytestmark = pytest.mark.gpu
 
-F64_TOL = 1e-12
-MASS_TOL = 1e-13
-# velocities are compared relative to max(max|u|, U_FLOOR): a case near rest
-# (gravity ~1e-5, 2 % density noise) has max|u| ~ 1e-4, where the rounding
-# of O(0.1) populations alone is ~1e-16 absolute per step
-U_FLOOR = 1e-3
+# storage -> (field bound, mass-history bound, velocity floor).  Velocities
+# are compared relative to max(max|u|, floor): a case near rest (gravity
+# ~1e-5, 2 % density noise) has max|u| ~ 1e-4.  FP64 rounds populations of
+# O(0.1) to ~1e-17 absolute; FP32 storage rounds them to ~3e-8 (6e-8
+# relative, once per step), so velocities are resolved to ~1e-7 absolute,
+# which is the FP32 bound 1e-5 times its floor 1e-2.
+TOL = {"f64": (1e-12, 1e-13, 1e-3), "f32": (1e-5, 1e-6, 1e-2)}
 
 
 def say(*a):
@@ -35,10 +37,12 @@ def L():
     return lbm
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("k", range(N_CASES))
-def test_random_case_matches_oracle(L, k):
+def test_random_case_matches_oracle(L, k, storage):
     p, tile_w, tile_h = random_case(k)
-    say(f"[gpu] random case {k}: {p.nx}x{p.ny} {p.rule}/{p.fix} eos={p.eos} "
+    tol, mass_tol, u_floor = TOL[storage]
+    say(f"[gpu] random case {k} {storage}: {p.nx}x{p.ny} {p.rule}/{p.fix} eos={p.eos} "
         f"{p.collision} tau={p.tau:.3f} g={p.gravity} tiles {tile_w}x{tile_h}")
     o = ora.Oracle(p)
     m0 = o.total_mass()
@@ -47,13 +51,17 @@ def test_random_case_matches_oracle(L, k):
         bad = None
     except ora.OracleError:
         bad = o.t
-    with L.Domain(p, storage="f64", tile_w=tile_w, tile_h=tile_h, history_capacity=256) as d:
+    with L.Domain(p, storage=storage, tile_w=tile_w, tile_h=tile_h,
+                  history_capacity=256) as d:
         if bad is not None:
             with pytest.raises(L.LbmError) as e:
                 d.step(STEPS)
             assert e.value.code == L.LBM_EUNSTABLE
-            assert L.lbm_unstable_step(d.h) == bad
-            say(f"    both unstable at step {bad}")
+            u = L.lbm_unstable_step(d.h)
+            say(f"    unstable at step {u} (oracle: {bad})")
+            # FP64 storage breaks down at the oracle's step; FP32 rounding
+            # may move the blow-up by a step or two
+            assert u == bad if storage == "f64" else abs(u - bad) <= 2
             return
         d.step(STEPS)
         got = d.moments()
@@ -61,13 +69,13 @@ def test_random_case_matches_oracle(L, k):
     ref = o.moments()
     fl = ~p.solid.astype(bool)
     umax = max(np.max(np.abs(ref[1][fl])), np.max(np.abs(ref[2][fl])))
-    scale = max(umax, U_FLOOR)
+    scale = max(umax, u_floor)
     e = [rel_err(got[0], ref[0], fl)] + \
         [float(np.max(np.abs(got[i][fl] - ref[i][fl]))) / scale for i in (1, 2)]
     oh = np.concatenate([[m0], hist])
     dm = float(np.max(np.abs(gh - oh) / np.abs(oh)))
     say(f"    rel err rho {e[0]:.2e} ux {e[1]:.2e} uy {e[2]:.2e} (max|u| {umax:.1e}) "
         f"mass {dm:.2e}")
-    assert max(e) <= F64_TOL
+    assert max(e) <= tol
     assert np.all(got[0][~fl] == 0)
-    assert gh.size == STEPS + 1 and dm <= MASS_TOL
+    assert gh.size == STEPS + 1 and dm <= mass_tol
