@@ -79,3 +79,37 @@ def test_random_case_matches_oracle(L, k, storage):
     assert max(e) <= tol
     assert np.all(got[0][~fl] == 0)
     assert gh.size == STEPS + 1 and dm <= mass_tol
+
+
+@pytest.mark.parametrize("persistent,graph", [(1, 8), (0, 0)])
+@pytest.mark.parametrize("eos", ["none", "exp", "cs"])
+def test_random_cases_batched_equal_alone(L, eos, persistent, graph):
+    """The sweep's cases of one EOS as one FP64 batch (a batch holds one
+    EOS): every instance ends with the fields, mass history and unstable
+    step of the same problem run alone at the batch's launch shape."""
+    cases = [random_case(k) for k in range(N_CASES)]
+    probs = [c[0] for c in cases if c[0].eos == eos]
+    say(f"[gpu] random cases, eos {eos}: {len(probs)} instances, persistent={persistent} "
+        f"graph={graph}")
+    with L.Batch(storage="f64", eos=eos, max_instances=N_CASES, tile_w=128, tile_h=16,
+                 persistent=persistent, graph_steps=graph, arena_bytes=1 << 29) as b:
+        slots = [b.add(p, STEPS, history_capacity=256) for p in probs]
+        b.run(STEPS + 3)
+        b.sync()
+        for s, p in zip(slots, probs):
+            t, rem, u = b.status(s)
+            g, h = b.moments(s), b.mass_history(s)
+            # an unstable instance stops at its first non-finite mass: the
+            # domain alone runs to that step
+            n = STEPS if u < 0 else u
+            with L.Domain(p, storage="f64", tile_w=128, tile_h=16, history_capacity=256) as d:
+                try:
+                    d.step(n)
+                except L.LbmError as e:
+                    assert e.code == L.LBM_EUNSTABLE
+                a_u = L.lbm_unstable_step(d.h)
+                a = d.moments()
+                ah = d.mass_history()
+            assert rem == 0 and u == a_u and t == n, (p.name, t, rem, u, a_u)
+            assert all(np.array_equal(g[i], a[i], equal_nan=True) for i in range(3)), p.name
+            assert np.array_equal(h, ah, equal_nan=True), p.name
