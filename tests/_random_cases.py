@@ -76,3 +76,40 @@ def random_case(k):
     p = Problem(nx=nx, ny=ny, solid=solid, links=links, rho0=rho0, rho_wall=rho_wall,
                 name=f"random{k}", **kw)
     return p, tile_w, tile_h
+
+
+def random_open_case(k):
+    """Flow past one or two discs between a velocity inlet (x = 0) and a
+    fully developed outlet, periodic in y, single phase: lattice size,
+    discs (clear of the three columns next to either end), inlet speed,
+    rule and fix, BGK or MRT, tau.  Seeded with 2000 + k."""
+    rng = np.random.default_rng(2000 + k)
+    nx, ny = int(rng.integers(40, 121)), int(rng.integers(32, 97))
+    rule = str(rng.choice(RULES))
+    fixes = ["none", "A"] + (["B", "bao"] if rule in ("fh", "mls") else [])
+    fix = str(rng.choice(fixes))
+    collision = str(rng.choice(["bgk", "mrt"]))
+    tau = float(rng.uniform(0.55, 1.2))
+    if rule == "fh" and abs(tau - 1.0) < 0.1:
+        tau = 0.8  # Eq. 9 is singular at tau = 1
+    U = float(rng.uniform(0.01, 0.1))
+    discs, n = [], int(rng.integers(1, 3))
+    for _ in range(200):
+        if len(discs) == n:
+            break
+        R = rng.uniform(3.0, max(3.5, min(nx, ny) / 6.0))
+        cx = rng.uniform(R + 6.0, nx - R - 7.0)
+        cy = rng.uniform(R + 2.0, ny - R - 3.0)
+        if any(np.hypot(cx - c.cx, cy - c.cy) < R + c.R + 4.0 for c in discs):
+            continue
+        discs.append(geo.Circle(cx, cy, R))
+    solid, owner, links = geo.build(nx, ny, discs)
+    fl = ~solid.astype(bool)
+    tile_w = int(rng.choice([64, 128, 256]))
+    tile_h = int(rng.integers(1, 21))
+    p = Problem(nx=nx, ny=ny, solid=solid, links=links,
+                rho0=1.0 + 0.01 * rng.random((ny, nx)), rho_wall=np.ones((ny, nx)),
+                eos="none", collision=collision, tau=tau, mrt_s=cfg.mrt_rates(tau),
+                rule=rule, fix=fix, ux0=np.where(fl, U, 0.0), uy0=np.zeros((ny, nx)),
+                open_x=True, inlet_u=U, name=f"random_open{k}")
+    return p, tile_w, tile_h

@@ -12,7 +12,7 @@ import pytest
 from oracle import core as ora
 from tests._lib import rel_err
 from tests._random_cases import random_case
-from tests.test_random_cases import N_CASES, STEPS
+from tests.test_random_cases import N_CASES, N_OPEN, OPEN_STEPS, STEPS
 
 pytestmark = pytest.mark.gpu
 
@@ -113,3 +113,27 @@ def test_random_cases_batched_equal_alone(L, eos, persistent, graph):
             assert rem == 0 and u == a_u and t == n, (p.name, t, rem, u, a_u)
             assert all(np.array_equal(g[i], a[i], equal_nan=True) for i in range(3)), p.name
             assert np.array_equal(h, ah, equal_nan=True), p.name
+
+
+@pytest.mark.parametrize("k", range(N_OPEN))
+def test_random_open_case_matches_oracle(L, k):
+    """Seeded flows past one or two discs with the open x boundaries:
+    fields, mass history and the wall force (momentum exchange) in FP64."""
+    from tests._random_cases import random_open_case
+    p, tile_w, tile_h = random_open_case(k)
+    say(f"[gpu] random open case {k}: {p.nx}x{p.ny} {p.rule}/{p.fix} {p.collision} "
+        f"tau={p.tau:.3f} U={p.inlet_u:.3f} tiles {tile_w}x{tile_h}")
+    o = ora.Oracle(p)
+    m0 = o.total_mass()
+    hist = o.step(OPEN_STEPS)
+    ref, F_o = o.moments(), o.wall_force()
+    with L.Domain(p, storage="f64", tile_w=tile_w, tile_h=tile_h, history_capacity=256) as d:
+        d.step(OPEN_STEPS)
+        got, F, gh = d.moments(), d.wall_force(), d.mass_history()
+    fl = ~p.solid.astype(bool)
+    e = [rel_err(got[i], ref[i], fl) for i in range(3)]
+    ef = float(np.max(np.abs(F - F_o)) / np.max(np.abs(F_o)))
+    oh = np.concatenate([[m0], hist])
+    dm = float(np.max(np.abs(gh - oh) / np.abs(oh)))
+    say(f"    rel err rho {e[0]:.2e} ux {e[1]:.2e} uy {e[2]:.2e} force {ef:.2e} mass {dm:.2e}")
+    assert max(e) <= 1e-12 and ef <= 1e-11 and dm <= 1e-13
