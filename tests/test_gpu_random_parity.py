@@ -3,7 +3,8 @@ discs (some rotating) and a flat wall with arbitrary wall fractions, every
 rule and the fixes it admits, no EOS / exponential / Carnahan-Starling with
 a droplet, BGK or MRT, a body force, and the launch shape, against the
 oracle after 60 steps (or at the first unstable step): FP64 storage
-within 1e-12, FP32 storage (FP64 arithmetic) within 1e-5."""
+within 1e-12, FP32 storage (FP64 arithmetic) within 1e-5, the FP32- and
+FP16-arithmetic forms within the bounds they are held to elsewhere."""
 import sys
 
 import numpy as np
@@ -22,7 +23,13 @@ pytestmark = pytest.mark.gpu
 # O(0.1) to ~1e-17 absolute; FP32 storage rounds them to ~3e-8 (6e-8
 # relative, once per step), so velocities are resolved to ~1e-7 absolute,
 # which is the FP32 bound 1e-5 times its floor 1e-2.
-TOL = {"f64": (1e-12, 1e-13, 1e-3), "f32": (1e-5, 1e-6, 1e-2)}
+# The reduced-precision forms take the bounds they are held to on the
+# droplet case (FP32 arithmetic 1e-5 / 3e-5, FP16 per-node 1e-3 / 1e-2),
+# with mass-history bounds from their stated drift.
+# storage -> (rho bound, u bound, mass-history bound, velocity floor)
+TOL = {"f64": (1e-12, 1e-12, 1e-13, 1e-3), "f32": (1e-5, 1e-5, 1e-6, 1e-2),
+       "f32_arith32": (1e-5, 3e-5, 1e-5, 1e-2), "f32dev": (1e-5, 3e-5, 1e-6, 1e-2),
+       "f16node": (1e-3, 1e-2, 2e-5, 1e-2)}
 
 
 def say(*a):
@@ -37,11 +44,11 @@ def L():
     return lbm
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32_arith32", "f32dev", "f16node"])
 @pytest.mark.parametrize("k", range(N_CASES))
 def test_random_case_matches_oracle(L, k, storage):
     p, tile_w, tile_h = random_case(k)
-    tol, mass_tol, u_floor = TOL[storage]
+    tol_r, tol_u, mass_tol, u_floor = TOL[storage]
     say(f"[gpu] random case {k} {storage}: {p.nx}x{p.ny} {p.rule}/{p.fix} eos={p.eos} "
         f"{p.collision} tau={p.tau:.3f} g={p.gravity} tiles {tile_w}x{tile_h}")
     o = ora.Oracle(p)
@@ -59,9 +66,9 @@ def test_random_case_matches_oracle(L, k, storage):
             assert e.value.code == L.LBM_EUNSTABLE
             u = L.lbm_unstable_step(d.h)
             say(f"    unstable at step {u} (oracle: {bad})")
-            # FP64 storage breaks down at the oracle's step; FP32 rounding
-            # may move the blow-up by a step or two
-            assert u == bad if storage == "f64" else abs(u - bad) <= 2
+            # FP64 storage breaks down at the oracle's step; reduced
+            # precision may move the blow-up by a few steps
+            assert u == bad if storage == "f64" else abs(u - bad) <= 3
             return
         d.step(STEPS)
         got = d.moments()
@@ -76,7 +83,7 @@ def test_random_case_matches_oracle(L, k, storage):
     dm = float(np.max(np.abs(gh - oh) / np.abs(oh)))
     say(f"    rel err rho {e[0]:.2e} ux {e[1]:.2e} uy {e[2]:.2e} (max|u| {umax:.1e}) "
         f"mass {dm:.2e}")
-    assert max(e) <= tol
+    assert e[0] <= tol_r and max(e[1:]) <= tol_u
     assert np.all(got[0][~fl] == 0)
     assert gh.size == STEPS + 1 and dm <= mass_tol
 
