@@ -357,7 +357,7 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             if constexpr (DEV == 2) {
                 rho_d = 0.0;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) rho_d += double(Lc.f[q]) + wt(q) * double(rr[q]);
+                for (int q = 0; q < 9; ++q) rho_d += fma(wt(q), double(rr[q]), double(Lc.f[q]));
             }
             msum += live ? rho_d : 0.0;
             // moments of boundary nodes (and pre-collision populations)
