@@ -222,6 +222,13 @@ int lbm_kernel_times(lbm_domain *d, double *main_ms, int64_t *main_count,
  * step. */
 int lbm_wall_force(lbm_domain *d, double out[2]);
 
+/* Scheme A (Eq. 18) adds a node's leak to its rest population, which can
+ * then turn negative; nothing clamps it.  *count receives the number of
+ * (boundary node, step) pairs where it did, since creation or the last
+ * lbm_set_state (0 under the other fixes).  Waits for the domain's
+ * stream. */
+int lbm_negative_rest(lbm_domain *d, int64_t *count);
+
 /* Facts about the built domain: [0] fluid nodes, [1] cut links,
  * [2] boundary nodes, [3] bytes of device memory held, [4] tile_w,
  * [5] tile_h, [6] main-kernel workgroups, [7] boundary-rule fallbacks

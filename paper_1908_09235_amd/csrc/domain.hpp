@@ -61,6 +61,7 @@ struct lbm_domain {
     int open_x = 0;        // velocity inlet at x = 0, outlet at x = nx - 1
     double inlet_u = 0.0;
     double* force = nullptr;   // wall force partials, two per link block
+    unsigned long long* negrest = nullptr;  // scheme A: negative rest count
     bool force_valid = false;  // a boundary pass has written them
     int nb = 0, nl = 0;
     int nslot_links = 0;

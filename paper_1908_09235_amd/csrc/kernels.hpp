@@ -540,6 +540,9 @@ struct BndArgs {
     int open_x;
     int nx, ny, pitch;
     double inlet_u;
+    // scheme A: count of boundary nodes whose rest population came out
+    // negative (null: not counted)
+    unsigned long long* __restrict__ negrest;
 };
 
 constexpr int LK_PAD = 15;
@@ -674,7 +677,16 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
             out_sum += s_fab[tid + m];
             in_sum += s_inc[tid + m] + s_wall[tid + m];
         }
-        A[node] = S(double(A[node]) + (out_sum - in_sum));
+        const double v = double(A[node]) + (out_sum - in_sum);
+        A[node] = S(v);
+        if (b.negrest) {
+            // Eq. (18) can leave the rest population negative: counted,
+            // not clamped
+            double f0 = v;
+            if constexpr (DEV == 2) f0 += wt(0) * double(rpl[node]);
+            if constexpr (DEV == 1) f0 += wt(0) * b.rref;
+            if (f0 < 0.0) atomicAdd(b.negrest, 1ull);
+        }
     }
     if (b.force) {
         // momentum handed to the wall by this link, e_a (f*_a + f_abar(t+1)),
@@ -964,6 +976,7 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.unstable = nullptr;
         a.do_reduce = 0;
         a.force = nullptr;
+        a.negrest = nullptr;
         a.nlink_blocks = 0;
         a.open_x = 0;
         a.nx = a.ny = a.pitch = 0;

@@ -179,6 +179,7 @@ BndArgs bnd_args(lbm_domain* d) {
     b.t = d->pending_t;
     b.slot = d->pending_t % d->cap;
     b.force = d->force;
+    b.negrest = d->negrest;
     b.nlink_blocks = link_blocks(d);
     b.open_x = d->open_x;
     b.nx = d->nx;
@@ -614,6 +615,9 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
                         (size_t)2 * std::max(link_blocks(d), 1) * 8)))
         return rc;
 
+    if ((rc = dev_alloc(d, (void**)&d->negrest, 8))) return rc;
+    if (hipMemsetAsync(d->negrest, 0, 8, d->stream) != hipSuccess) return LBM_EDEVICE;
+
     const long long minus1 = -1;
     if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
         return LBM_EDEVICE;
@@ -939,6 +943,7 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
         return LBM_EDEVICE;
     p += (size_t)d->cap * 8;
     if (hipMemcpy(d->unstable, p, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemset(d->negrest, 0, 8) != hipSuccess) return LBM_EDEVICE;
     d->t = (long long)hdr[1];
     d->pending = false;
     d->pending_t = d->t;
@@ -969,6 +974,16 @@ int lbm_kernel_times(lbm_domain* d, double* main_ms, int64_t* main_count, double
     if (main_count) *main_count = d->main_n;
     if (boundary_ms) *boundary_ms = d->bnd_ms;
     if (boundary_count) *boundary_count = d->bnd_n;
+    return LBM_OK;
+}
+
+int lbm_negative_rest(lbm_domain* d, int64_t* count) {
+    if (!d || !count) return LBM_EINVAL;
+    unsigned long long n = 0;
+    if (hipMemcpyAsync(&n, d->negrest, 8, hipMemcpyDeviceToHost, d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    *count = (int64_t)n;
     return LBM_OK;
 }
 

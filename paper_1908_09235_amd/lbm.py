@@ -85,6 +85,7 @@ EXPORTS = {
     "lbm_kernel_times": (C.c_int, [_H, _D, C.POINTER(C.c_int64), _D,
                                    C.POINTER(C.c_int64)]),
     "lbm_info": (C.c_int, [_H, C.POINTER(C.c_int64)]),
+    "lbm_negative_rest": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_destroy": (None, [_H]),
     "lbm_status_string": (C.c_char_p, [C.c_int]),
     "lbm_batch_create": (C.c_int, [C.POINTER(lbm_batch_desc), C.POINTER(_H)]),
@@ -275,6 +276,12 @@ def lbm_kernel_times(h):
     return mm.value, mn.value, bm.value, bn.value
 
 
+def lbm_negative_rest(h):
+    n = C.c_int64()
+    _check(lib().lbm_negative_rest(h, C.byref(n)), "lbm_negative_rest")
+    return n.value
+
+
 def lbm_info(h):
     out = (C.c_int64 * 8)()
     _check(lib().lbm_info(h, out), "lbm_info")
@@ -326,6 +333,9 @@ class Domain:
 
     def info(self):
         return lbm_info(self.h)
+
+    def negative_rest(self):
+        return lbm_negative_rest(self.h)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -41,6 +41,7 @@ def test_null_arguments_are_rejected(L):
     assert lib.lbm_total_mass(None, None) == L.LBM_EINVAL
     assert lib.lbm_moments(None, None, None, None) == L.LBM_EINVAL
     assert lib.lbm_wall_force(None, None) == L.LBM_EINVAL
+    assert lib.lbm_negative_rest(None, None) == L.LBM_EINVAL
     n = ctypes.c_size_t()
     assert lib.lbm_get_state(None, None, ctypes.byref(n)) == L.LBM_EINVAL
     lib.lbm_destroy(None)

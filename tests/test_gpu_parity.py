@@ -386,3 +386,34 @@ def test_couette_convergence_on_gpu(L, fix):
     assert np.all(np.diff(errs) < 0)
     if fix == "none":
         assert np.all(orders > 1.5) and 1.7 < mean < 2.5
+
+
+@pytest.mark.parametrize("case", ["cfg1_zy", "wet_zy", "wet_ibbq", "cfg1_mls"])
+def test_scheme_a_negative_rest_population_count(L, case):
+    """Scheme A leaves some rest populations negative (counted, not
+    clamped); the library counts the same (node, step) pairs as the oracle.
+    In these cases it happens only as a run breaks down, so both run to the
+    oracle's first unstable step; the stable MLS case counts none."""
+    rl, _ = cfg.cs_init_densities(0.86)
+    p = {"cfg1_zy": lambda: cfg.cfg1("zhao_yong", "A"),
+         "wet_zy": lambda: cfg.droplet_on_cylinder(rule="zhao_yong", fix="A", rho_wall=rl,
+                                                   tau=1.0, name="wet_zy"),
+         "wet_ibbq": lambda: cfg.droplet_on_cylinder(rule="ibb_quadratic", fix="A",
+                                                     rho_wall=0.25, tau=1.0, name="wet_ibbq"),
+         "cfg1_mls": lambda: cfg.cfg1("mls", "A")}[case]()
+    o = ora.Oracle(p)
+    steps = 300
+    try:
+        o.step(steps)
+    except ora.OracleError:
+        steps = o.t
+    want = int(o.counters()[4])
+    with L.Domain(p, storage="f64") as d:
+        try:
+            d.step(steps)
+        except L.LbmError as e:
+            assert e.code == L.LBM_EUNSTABLE and steps < 300
+        got = d.negative_rest()
+    say(f"[gpu] {case}: {steps} steps, negative rest populations {got} (oracle {want})")
+    assert got == want
+    assert (want == 0) == (case == "cfg1_mls")
