@@ -94,13 +94,16 @@ enum lbm_storage {
     LBM_STORE_F16DEV = 4,      /* FP16 (IEEE binary16) deviations, FP32
                                   arithmetic                              */
     LBM_STORE_F16NODE = 5      /* FP16 deviations g_a = f_a - w_a r(x) from a
-                                  per-node reference r (x the node whose
-                                  slot holds g): the initial density rho0 at
-                                  fluid nodes, and at a solid node that
-                                  receives incoming populations, rho0 of a
-                                  fluid node next to it.  One FP32 read of r
-                                  per update on top of the FP16 traffic;
-                                  FP32 arithmetic; rho_ref is ignored      */
+                                  per-node reference r: the current density
+                                  of the node x whose slot holds g (an FP32
+                                  plane after the nine population planes,
+                                  rewritten by every update; a solid node
+                                  that receives incoming populations takes
+                                  the density of one fluid node next to it;
+                                  initially rho0).  One FP32 read and one
+                                  write of r per update on top of the FP16
+                                  traffic; FP32 arithmetic; rho_ref is
+                                  ignored                                 */
 };
 
 /* One cut link (40 bytes). */
