@@ -11,7 +11,8 @@ with FP32 populations (FP64 arithmetic), the roofline of the main kernel
 (achieved HBM GB/s from its algorithmic bytes and its mean launch duration,
 timed with HIP events on its stream), the FP64-storage and FP32-arithmetic
 forms of the same workload, the precision forms on 8192 x 4096, the
-batched and served forms, the paper's other experiments (flow past a
+batched form (FP32 storage, and the same mix in FP64 storage) and the
+served form, the paper's other experiments (flow past a
 cylinder, gravity q-sweep, contact angle), and the CPU oracle timed on a
 bounded sample (one copy, then one independent copy per usable core at
 once, before the GPU is touched).
@@ -234,7 +235,8 @@ def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
     """The batched mix: n_inst droplet-on-cylinder instances (sides
     64..768, T/Tc, tau drawn per instance), one batch, autotuned, each
     instance run `steps` steps.  Sampled instances are checked against the
-    FP64 plain form; a sample run one by one gives the unbatched rate."""
+    FP64 plain form; a sample run one by one gives the unbatched rate
+    (alone_steps 0: not measured)."""
     import numpy as np
     import torch
 
@@ -285,6 +287,8 @@ def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
                      **rel_err_fields(probs[k], g, ref)})
     out["sample_vs_fp64"] = errs
     b.close()
+    if alone_steps <= 0:
+        return out
     # the unbatched rate: a sample of instances one after another, one
     # domain and two launches per step each
     k_alone = list(range(0, n_inst, max(1, n_inst // 16)))
@@ -486,6 +490,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5000,
                     help="steps of each instance of the batched mix (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=512)
+    ap.add_argument("--batch-f64", type=int, default=1,
+                    help="also run the batched mix in FP64 storage (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="arrival window of each served run (0: skip)")
     ap.add_argument("--serve-chunk", type=int, default=100)
@@ -566,6 +572,11 @@ def main():
     if a.batch_steps > 0:
         batch = batch_leg(a.batch_steps, a.batch_instances, "f32", stream, 3,
                           [0, 101, 257, a.batch_instances - 1], 500)
+        if a.batch_f64:
+            # the same mix in FP64 storage: the accuracy gate holds by
+            # construction (the samples must match the plain form exactly)
+            batch["fp64_storage"] = batch_leg(a.batch_steps, a.batch_instances, "f64",
+                                              stream, 3, [0, 257], 0)
     serve = None
     if a.serve_seconds > 0:
         serve = serve_leg("f32", a.serve_seconds, [0.5, 0.8, 1.0], a.serve_chunk, 128)
