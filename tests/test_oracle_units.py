@@ -5,6 +5,7 @@ import pytest
 
 from oracle import core as ora
 from oracle import eos as oeos
+from lbm_inputs.problem import LINK_DTYPE, Problem
 
 EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
 EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], float)
@@ -253,3 +254,59 @@ def test_moving_wall_halfway_is_ladd():
         got = _rule("halfway", 0.5, dir=d, fa_b=fa, rho_b=rho, uwy=uw)
         want = ora.feq(rho, 0.0, uw)[OPP[d]]
         assert abs(got - want) < 1e-16
+
+
+# --------------------------------------------- MRT forcing, non-conserved moments
+def _ll_basis():
+    """Lallemand-Luo rows written out from their polynomials in the lattice
+    velocity (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy)."""
+    c2 = EX * EX + EY * EY
+    return np.array([np.ones(9), -4 + 3 * c2, 4 - 10.5 * c2 + 4.5 * c2 * c2,
+                     EX, (-5 + 3 * c2) * EX, EY, (-5 + 3 * c2) * EY,
+                     EX * EX - EY * EY, EX * EY])
+
+
+@pytest.mark.parametrize("rho0", [1.0, 0.37])
+def test_mrt_forced_box_fixed_point(rho0):
+    """MRT forcing on the non-conserved moments, pinned by a fixed point.
+
+    A spatially uniform, periodic fluid under a constant body force has no
+    streaming: each step maps the moments m to
+    m - S (m - m_eq) + (I - S/2) M Fbar, while the momentum grows by exactly
+    F, so u grows by F/rho and the equilibrium moments grow by
+    dm_eq = (0, 6u.F, -6u.F, F_x, -F_x, F_y, -F_y, 2(u_x F_x - u_y F_y),
+    u_x F_y + u_y F_x) + O(F^2) per step -- which is the Guo source M Fbar
+    itself.  The non-equilibrium part n = m - m_eq therefore settles where
+    s n = (1 - s/2) M Fbar - dm_eq, i.e. n = -M Fbar / 2 whatever the rate
+    s of the moment.  A prefactor (1 - 1/(2 tau)) in place of (1 - s/2)
+    would settle at -M Fbar / (2 tau s) instead, which the rates below keep
+    at least 10 % away."""
+    tau = 0.8
+    s = (1.0, 1.1, 1.6, 1.0, 1.4, 1.0, 1.45, 1 / tau, 1 / tau)
+    for i in (1, 2, 4, 6):
+        assert abs(1.0 / (2 * tau * s[i]) - 0.5) > 0.05
+    n = 4
+    g = (1.0e-6, -0.7e-6)
+    u0 = (0.05, -0.03)
+    p = Problem(nx=n, ny=n, solid=np.zeros((n, n), np.uint8),
+                links=np.zeros(0, dtype=LINK_DTYPE), rho0=np.full((n, n), rho0),
+                rho_wall=np.ones((n, n)), eos="none", tau=tau, gravity=g,
+                collision="mrt", mrt_s=s, ux0=np.full((n, n), u0[0]),
+                uy0=np.full((n, n), u0[1]), name="forced_box")
+    o = ora.Oracle(p)
+    o.step(300)   # the start f_eq(rho0, u0) has n = 0; |1 - s| <= 0.6 per step
+    f = o.get_f()[:, 1, 2]
+    rho = f.sum()
+    Fx, Fy = rho * g[0], rho * g[1]
+    ux = (f @ EX + 0.5 * Fx) / rho           # Eq. (5)
+    uy = (f @ EY + 0.5 * Fy) / rho
+    usq = ux * ux + uy * uy
+    m_eq = np.array([rho, -2 * rho + 3 * rho * usq, rho - 3 * rho * usq,
+                     rho * ux, -rho * ux, rho * uy, -rho * uy,
+                     rho * (ux * ux - uy * uy), rho * ux * uy])
+    src = np.array([0.0, 6 * (ux * Fx + uy * Fy), -6 * (ux * Fx + uy * Fy),
+                    Fx, -Fx, Fy, -Fy, 2 * (ux * Fx - uy * Fy), ux * Fy + uy * Fx])
+    neq = _ll_basis() @ f - m_eq
+    for i in (1, 2, 4, 6, 7, 8):
+        # O(F^2) and rounding are ~1e-12 against |src| >= 7e-8
+        assert abs(neq[i] + 0.5 * src[i]) <= 1e-4 * abs(src[i]), (i, neq[i], -0.5 * src[i])
