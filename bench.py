@@ -59,8 +59,11 @@ def traffic_record(storage, workload):
     return r["bytes_per_launch"]
 
 
-def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_every,
+def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_steps,
             moments=False):
+    """Warm up, then time `steps` steps (captured step graphs, no events);
+    then a separate pass of `prof_steps` steps with HIP events around every
+    launch on the library's stream gives the mean kernel durations."""
     import torch
 
     from paper_1908_09235_amd import lbm
@@ -68,21 +71,28 @@ def run_gpu(p, storage, steps, warmup, stream, tile_w, tile_h, prof_every,
     d = lbm.Domain(p, storage=storage, stream=stream, tile_w=tile_w, tile_h=tile_h,
                    history_capacity=1 << 16)
     info = d.info()
-    d.step(warmup)
+    d.step(warmup)  # also captures the step graphs the timed run replays
     torch.cuda.synchronize()
-    lbm.lbm_set_profiling(d.h, prof_every)
     t0 = time.perf_counter()
-    lbm.lbm_step(d.h, steps)
+    lbm.lbm_step_async(d.h, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    main_ms, main_n, bnd_ms, bnd_n = lbm.lbm_kernel_times(d.h)
-    lbm.lbm_set_profiling(d.h, 0)
+    lbm.lbm_sync(d.h)  # raises if a step was unstable
     hist = d.mass_history(steps + 1)
     drift = float(abs(hist[-1] - hist[0]) / hist[0])
     mom = d.moments() if moments else None
+    main_ms = bnd_ms = 0.0
+    main_n = 0
+    if prof_steps > 0:
+        lbm.lbm_set_profiling(d.h, 1)
+        lbm.lbm_step(d.h, prof_steps)
+        main_ms, main_n, bnd_ms, bnd_n = lbm.lbm_kernel_times(d.h)
+        lbm.lbm_set_profiling(d.h, 0)
+        main_ms /= max(main_n, 1)
+        bnd_ms /= max(bnd_n, 1)
     d.close()
-    return dict(seconds=t1 - t0, info=info, main_ms=main_ms / max(main_n, 1),
-                bnd_ms=bnd_ms / max(bnd_n, 1), samples=main_n, drift=drift, mom=mom)
+    return dict(seconds=t1 - t0, info=info, main_ms=main_ms, bnd_ms=bnd_ms, samples=main_n,
+                drift=drift, mom=mom)
 
 
 def copy_bandwidth(torch, mib=1024, reps=20):
@@ -103,7 +113,7 @@ def copy_bandwidth(torch, mib=1024, reps=20):
     return round(2 * (mib << 20) / (ms * 1e-3) / 1e9, 1)
 
 
-def precision_leg(steps, warmup, stream, prof_every):
+def precision_leg(steps, warmup, stream, prof_steps):
     """Many cylinders with droplets, 8192 x 4096, CS at 0.86 Tc, BGK
     tau = 0.8, MLS + B: each storage form run from the same start for the
     same steps; errors of rho and u (max-norm relative, fluid nodes)
@@ -117,7 +127,7 @@ def precision_leg(steps, warmup, stream, prof_every):
     out = {"workload": f"{p.name}_bgk_mls_B", "steps": steps}
     ref = None
     for st in ("f64", "f32", "f32dev", "f16dev", "f16node"):
-        r = run_gpu(p, st, steps, warmup, stream, 0, 0, prof_every, moments=True)
+        r = run_gpu(p, st, steps, warmup, stream, 0, 0, prof_steps, moments=True)
         fluid = r["info"]["fluid_nodes"]
         rec = {"arith": ARITH[st],
                "mlups": round(fluid * steps / r["seconds"] / 1e6, 1),
@@ -476,10 +486,11 @@ def main():
                     help="droplet geometry scale (16 = 2048 x 2048)")
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
-    ap.add_argument("--prof-every", type=int, default=50,
-                    help="time the kernels of every n-th step with HIP events "
-                         "(events between the launches of every step would "
-                         "add their own cost to the timed steps)")
+    ap.add_argument("--prof-steps", type=int, default=100,
+                    help="steps of the separate pass that times every launch "
+                         "with HIP events, after the timed region (events "
+                         "between launches would add their own cost to the "
+                         "timed steps)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle copies run at once for the all-cores rate "
@@ -540,7 +551,7 @@ def main():
         torch.cuda.synchronize()
 
     copy_gbs = copy_bandwidth(torch)
-    r = run_gpu(p, a.storage, a.steps, a.warmup, stream, a.tile_w, a.tile_h, a.prof_every)
+    r = run_gpu(p, a.storage, a.steps, a.warmup, stream, a.tile_w, a.tile_h, a.prof_steps)
     fluid = r["info"]["fluid_nodes"]
     s = BYTES_PER_POP[a.storage]
     mlups = fluid * a.steps / r["seconds"] / 1e6
@@ -553,7 +564,7 @@ def main():
         if st == a.storage or a.other_steps <= 0:
             continue
         ro = run_gpu(p, st, a.other_steps, a.warmup, stream, a.tile_w, a.tile_h,
-                     a.prof_every)
+                     a.prof_steps)
         so = BYTES_PER_POP[st]
         also[st] = {
             "storage": st, "arith": ARITH[st],
@@ -566,7 +577,7 @@ def main():
 
     prec = None
     if a.precision_steps > 0:
-        prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_every)
+        prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_steps)
 
     batch = None
     if a.batch_steps > 0:

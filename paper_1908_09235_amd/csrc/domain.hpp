@@ -69,9 +69,18 @@ struct lbm_domain {
         *lxff = nullptr, *lslotb = nullptr, *lslotf = nullptr;
     double *lc = nullptr, *luw = nullptr;
     long long cap = 0, t = 0;
+    long long* clock = nullptr;  // device: step of the last recorded mass
     bool pending = false;
     long long pending_t = 0;
     hipStream_t stream = nullptr;
+    int device = 0;              // the GPU the domain lives on
+    // Captured runs of 2^k steps (k = 0 .. kGraphLevels - 1), per parity of
+    // the buffer that holds f*(t) when the run starts; built on first use
+    // on a capture stream of the domain's own and replayed on `stream`.
+    static constexpr int kGraphLevels = 6;
+    hipGraphExec_t graphs[2][kGraphLevels] = {};
+    hipStream_t cap_stream = nullptr;
+    bool graphs_off = false;     // capture failed once: plain launches
     lbm::Phys<double> ph64{};
     lbm::Phys<float> ph32{};
     size_t bytes = 0;

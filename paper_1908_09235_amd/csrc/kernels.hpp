@@ -449,11 +449,9 @@ __global__ __launch_bounds__(256) void k_main(MainArgs<S> a, Phys<R> ph) {
     main_tile<S, R, EOS, MOMENTS, DEV, SAVEF>(a, ph, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-// Sum the main kernel's partials in a fixed order into the history ring.
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ partial,
-                                                int np, double* __restrict__ hist,
-                                                long long slot, long long t,
-                                                long long* __restrict__ unstable) {
+// Sum the main kernel's partials in a fixed order; the total lands in
+// thread 0.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int np) {
     __shared__ double red[256];
     const int tid = threadIdx.x;
     // each thread adds partials tid, tid + 256, ... in that order; eight
@@ -474,18 +472,43 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
         if (tid < s) red[tid] += red[tid + s];
         __syncthreads();
     }
-    if (tid == 0) {
-        const double m = red[0];
+    return red[0];
+}
+
+// The total into hist[slot], and the first non-finite one into unstable.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partial,
+                                                int np, double* __restrict__ hist,
+                                                long long slot, long long t,
+                                                long long* __restrict__ unstable) {
+    const double m = sum_partials(partial, np);
+    if (threadIdx.x == 0) {
         hist[slot] = m;
         if (!isfinite(m) && *unstable < 0) *unstable = t;
     }
 }
 
+// As reduce_partials, with the step taken from a device clock that holds
+// the step of the last recorded mass and advances by one: the launches of
+// a step then need no argument that changes from step to step, so a
+// captured graph of steps can be replayed.
+__device__ __forceinline__ void reduce_on_clock(const double* __restrict__ partial, int np,
+                                                double* __restrict__ hist, long long cap,
+                                                long long* __restrict__ clock,
+                                                long long* __restrict__ unstable) {
+    const double m = sum_partials(partial, np);
+    if (threadIdx.x == 0) {
+        const long long t = *clock + 1;
+        hist[t % cap] = m;
+        if (!isfinite(m) && *unstable < 0) *unstable = t;
+        *clock = t;
+    }
+}
+
 template <int Unused = 0>
 __global__ __launch_bounds__(256) void k_reduce(const double* partial, int np,
-                                                double* hist, long long slot,
-                                                long long t, long long* unstable) {
-    reduce_partials(partial, np, hist, slot, t, unstable);
+                                                double* hist, long long cap,
+                                                long long* clock, long long* unstable) {
+    reduce_on_clock(partial, np, hist, cap, clock, unstable);
 }
 
 // ---------------------------------------------------------------- boundary
@@ -528,7 +551,8 @@ struct BndArgs {
     const double* __restrict__ partial;
     int np;
     double* __restrict__ hist;
-    long long slot, t;
+    long long cap;                   // history ring entries
+    long long* __restrict__ clock;   // step of the last recorded mass
     long long* __restrict__ unstable;
     int do_reduce;
     // force on the walls (Sec. 4.2, momentum exchange): two FP64 partials
@@ -758,7 +782,7 @@ __device__ __forceinline__ void open_rows(S* __restrict__ A, const BndArgs& b, i
 template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
     if (blockIdx.x == gridDim.x - 1) {
-        if (b.do_reduce) reduce_partials(b.partial, b.np, b.hist, b.slot, b.t, b.unstable);
+        if (b.do_reduce) reduce_on_clock(b.partial, b.np, b.hist, b.cap, b.clock, b.unstable);
         return;
     }
     if (int(blockIdx.x) >= b.nlink_blocks) {
@@ -971,8 +995,8 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.partial = nullptr;
         a.np = 0;
         a.hist = nullptr;
-        a.slot = 0;
-        a.t = 0;
+        a.cap = 1;
+        a.clock = nullptr;
         a.unstable = nullptr;
         a.do_reduce = 0;
         a.force = nullptr;

@@ -41,7 +41,8 @@ void launch_init_f64(const Ctx& c, const double* rho_wall, const double* rho0,
                      const double* ux0, const double* uy0, void* buf, void* other);
 void launch_init_f32(const Ctx& c, const double* rho_wall, const double* rho0,
                      const double* ux0, const double* uy0, void* buf, void* other);
-void launch_reduce(const Ctx& c, long long slot, long long t, double* hist,
+// the main pass's partials into hist[(clock + 1) % cap]; clock += 1
+void launch_reduce(const Ctx& c, long long cap, long long* clock, double* hist,
                    long long* unstable);
 
 // One step of a batch: boundary and main passes (per storage precision),

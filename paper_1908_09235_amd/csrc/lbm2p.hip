@@ -56,6 +56,14 @@ int upload(lbm_domain* d, T** dst, const std::vector<T>& src) {
     return LBM_OK;
 }
 
+void drop_graphs(lbm_domain* d) {
+    for (auto& row : d->graphs)
+        for (hipGraphExec_t& g : row) {
+            if (g) (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
 void free_domain(lbm_domain* d) {
     if (!d) return;
     // queued work on the domain's stream may still use the memory
@@ -66,6 +74,8 @@ void free_domain(lbm_domain* d) {
         for (void* p : d->allocs) (void)hipFree(p);
     }
     for (hipEvent_t e : d->ev) (void)hipEventDestroy(e);
+    drop_graphs(d);
+    if (d->cap_stream) (void)hipStreamDestroy(d->cap_stream);
     delete d;
 }
 
@@ -176,8 +186,8 @@ BndArgs bnd_args(lbm_domain* d) {
     b.hist = d->hist;
     b.unstable = d->unstable;
     b.do_reduce = d->pending ? 1 : 0;
-    b.t = d->pending_t;
-    b.slot = d->pending_t % d->cap;
+    b.cap = d->cap;
+    b.clock = d->clock;
     b.force = d->force;
     b.negrest = d->negrest;
     b.nlink_blocks = link_blocks(d);
@@ -201,7 +211,7 @@ void launch_boundary(lbm_domain* d, void* cur) {
 
 void reduce_pending(lbm_domain* d) {
     if (!d->pending) return;
-    launch_reduce(ctx(d), d->pending_t % d->cap, d->pending_t, d->hist, d->unstable);
+    launch_reduce(ctx(d), d->cap, d->clock, d->hist, d->unstable);
     d->pending = false;
 }
 
@@ -232,31 +242,113 @@ int harvest(lbm_domain* d) {
     return LBM_OK;
 }
 
-int run_steps(lbm_domain* d, int64_t n) {
+// One step as plain launches: boundary pass on f*(t) (which also records
+// the previous step's mass), main pass f*(t) -> f*(t + 1).  With rec, HIP
+// events bracket both launches.
+void launch_step(lbm_domain* d, hipEvent_t* rec) {
+    void* cur = d->f[d->cur];
+    void* nxt = d->f[d->cur ^ 1];
+    if (rec) (void)hipEventRecord(rec[0], d->stream);
+    launch_boundary(d, cur);
+    if (rec) (void)hipEventRecord(rec[1], d->stream);
+    if (rec) (void)hipEventRecord(rec[2], d->stream);
+    launch_main(d, cur, nxt, false);
+    if (rec) (void)hipEventRecord(rec[3], d->stream);
+    d->cur ^= 1;
+    d->t += 1;
+    d->pending = true;
+    d->pending_t = d->t;
+}
+
+// Steps with kernel timing: plain launches, events on every prof-th step.
+// (the caller has reduced any pending mass)
+int run_steps_profiled(lbm_domain* d, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
-        void* cur = d->f[d->cur];
-        void* nxt = d->f[d->cur ^ 1];
-        const bool rec = d->prof > 0 && (d->t % d->prof) == 0;
+        const bool rec = (d->t % d->prof) == 0;
         if (rec && d->nrec == kProfPool) {
             int rc = harvest(d);
             if (rc) return rc;
         }
-        hipEvent_t* e = rec ? &d->ev[4 * d->nrec] : nullptr;
-        if (rec) (void)hipEventRecord(e[0], d->stream);
-        launch_boundary(d, cur);
-        if (rec) (void)hipEventRecord(e[1], d->stream);
-        if (rec) (void)hipEventRecord(e[2], d->stream);
-        launch_main(d, cur, nxt, false);
-        if (rec) (void)hipEventRecord(e[3], d->stream);
+        launch_step(d, rec ? &d->ev[4 * d->nrec] : nullptr);
         if (rec) d->nrec++;
-        d->cur ^= 1;
-        d->t += 1;
-        d->pending = true;
-        d->pending_t = d->t;
     }
     reduce_pending(d);
-    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
-    return LBM_OK;
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+// The graph of 2^level steps that starts with f*(t) in buffer `parity`:
+// the steps' launches and the closing reduction, captured on the domain's
+// capture stream (the kernels only read the step from the device clock,
+// so every replay continues where the last one stopped).  Null if capture
+// is not available.
+hipGraphExec_t step_graph(lbm_domain* d, int parity, int level) {
+    hipGraphExec_t& g = d->graphs[parity][level];
+    if (g || d->graphs_off) return g;
+    if (!d->cap_stream &&
+        hipStreamCreateWithFlags(&d->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        d->cap_stream = nullptr;
+        d->graphs_off = true;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    // replay the bookkeeping of plain launches on a copy of the host state
+    const int cur0 = d->cur;
+    const long long t0 = d->t, pt0 = d->pending_t;
+    const bool p0 = d->pending;
+    const hipStream_t s0 = d->stream;
+    d->cur = parity;
+    d->pending = false;
+    d->stream = d->cap_stream;
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        for (int k = 0; k < (1 << level); ++k) launch_step(d, nullptr);
+        reduce_pending(d);
+        ok = hipStreamEndCapture(d->stream, &graph) == hipSuccess && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    d->cur = cur0;
+    d->t = t0;
+    d->pending = p0;
+    d->pending_t = pt0;
+    d->stream = s0;
+    if (!ok) {
+        g = nullptr;
+        d->graphs_off = true;
+        (void)hipGetLastError();
+    }
+    return g;
+}
+
+// n steps: replays of captured runs of 32, 16, ..., 1 steps (plain
+// launches where capture is not available or kernels are being timed).
+int run_steps(lbm_domain* d, int64_t n) {
+    reduce_pending(d);  // every run below starts with no mass pending
+    if (d->prof > 0) return run_steps_profiled(d, n);
+    while (n > 0) {
+        int level = lbm_domain::kGraphLevels - 1;
+        while ((1LL << level) > n) --level;
+        const long long k = 1LL << level;
+        if (!d->graphs[d->cur][level] && !d->graphs_off) {
+            // all runs for both parities at once, so that later calls of
+            // any length replay without capturing
+            for (int par = 0; par < 2; ++par)
+                for (int lv = 0; lv < lbm_domain::kGraphLevels; ++lv) (void)step_graph(d, par, lv);
+        }
+        hipGraphExec_t g = d->graphs_off ? nullptr : d->graphs[d->cur][level];
+        if (g) {
+            if (hipGraphLaunch(g, d->stream) != hipSuccess) return LBM_EDEVICE;
+            d->cur ^= (int)(k & 1);
+            d->t += k;
+            d->pending_t = d->t;
+        } else {
+            for (long long i = 0; i < k; ++i) launch_step(d, nullptr);
+            reduce_pending(d);
+        }
+        n -= k;
+    }
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 
 int check_unstable(lbm_domain* d) {
@@ -598,6 +690,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->partial_cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
+    if ((rc = dev_alloc(d, (void**)&d->clock, 8))) return rc;
     // in an arena (batched and served instances) the read-out buffer is part
     // of the footprint, so that reading a finished instance never fails
     if (d->arena && (rc = dev_alloc(d, (void**)&d->mom_out, (size_t)3 * N * 8))) return rc;
@@ -618,8 +711,10 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if ((rc = dev_alloc(d, (void**)&d->negrest, 8))) return rc;
     if (hipMemsetAsync(d->negrest, 0, 8, d->stream) != hipSuccess) return LBM_EDEVICE;
 
-    const long long minus1 = -1;
-    if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
+    // no unstable step yet; the first recorded mass is that of step 0
+    static const long long minus1 = -1;
+    if (hipMemcpyAsync(d->unstable, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+        hipMemcpyAsync(d->clock, &minus1, 8, hipMemcpyHostToDevice, d->stream) != hipSuccess)
         return LBM_EDEVICE;
     if (hipMemsetAsync(d->hist, 0, (size_t)d->cap * 8, d->stream) != hipSuccess)
         return LBM_EDEVICE;
@@ -674,6 +769,8 @@ int domain_create(const lbm_desc* desc, Arena* arena, lbm_domain** out) {
     if (!d) return LBM_ENOMEM;
     d->arena = arena;
     int rc = validate_and_build(desc, d);
+    // (the descriptor is checked before anything touches the device)
+    if (rc == LBM_OK && hipGetDevice(&d->device) != hipSuccess) rc = LBM_EDEVICE;
     if (rc != LBM_OK) {
         free_domain(d);
         return rc;
@@ -690,6 +787,7 @@ int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h) {
     const int sc = strip_cols(tile_w);
     const int ns = (d->nx + sc - 1) / sc, ng = (d->ny + tile_h - 1) / tile_h;
     if ((long long)ns * ng > d->partial_cap) return LBM_EINVAL;
+    drop_graphs(d);
     d->tile_w = tile_w;
     d->tile_h = tile_h;
     d->nstrips = ns;
@@ -944,6 +1042,8 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
     p += (size_t)d->cap * 8;
     if (hipMemcpy(d->unstable, p, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     if (hipMemset(d->negrest, 0, 8) != hipSuccess) return LBM_EDEVICE;
+    const long long tclock = (long long)hdr[1];
+    if (hipMemcpy(d->clock, &tclock, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     d->t = (long long)hdr[1];
     d->pending = false;
     d->pending_t = d->t;

@@ -1,0 +1,64 @@
+"""Captured step graphs: lbm_step replays captured runs of 1, 2, 4, ..., 32
+steps; with kernel timing on it launches every kernel itself.  Both must
+give the same fields and mass history bit for bit, for run lengths of
+either parity and across a checkpoint."""
+import sys
+
+import numpy as np
+import pytest
+
+from lbm_inputs import configs as cfg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_09235_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+RUNS = (1, 2, 5, 37, 64, 3, 100)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_graph_replay_equals_plain_launches(L, storage):
+    p = cfg.cfg1("mls", "B")
+    say(f"[gpu] graphs vs plain launches, cfg1 MLS+B {storage}, runs {RUNS}")
+    with L.Domain(p, storage=storage, history_capacity=512) as g, \
+            L.Domain(p, storage=storage, history_capacity=512) as e:
+        L.lbm_set_profiling(e.h, 1)  # timed steps launch every kernel
+        for n in RUNS:
+            g.step(n)
+            e.step(n)
+            assert g.t == e.t
+            for a, b in zip(g.moments(), e.moments()):
+                assert np.array_equal(a, b), n
+            assert g.total_mass() == e.total_mass()
+        _, cnt, _, _ = L.lbm_kernel_times(e.h)
+        assert cnt == sum(RUNS)
+        assert np.array_equal(g.mass_history(), e.mass_history())
+
+
+def test_graph_replay_resumes_from_a_checkpoint(L):
+    p = cfg.cfg1("mls", "A")
+    say("[gpu] checkpoint at step 7, restored, 33 more steps by graph replay")
+    with L.Domain(p, storage="f64", history_capacity=64) as a:
+        a.step(7)
+        st = L.lbm_get_state(a.h)
+        a.step(33)
+        want = a.moments()
+        hw = a.mass_history()
+        a.step(5)
+        L.lbm_set_state(a.h, st)
+        assert a.t == 7
+        a.step(33)
+        for x, y in zip(a.moments(), want):
+            assert np.array_equal(x, y)
+        assert np.array_equal(a.mass_history(), hw)
