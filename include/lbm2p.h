@@ -191,6 +191,18 @@ int lbm_moments(lbm_domain *d, double *rho, double *ux, double *uy);
  * stream, without waiting. */
 int lbm_moments_device(lbm_domain *d, double *rho, double *ux, double *uy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): as
+ * lbm_moments_device, but staged through a buffer the library holds on
+ * every GPU it runs on from load time to process exit (3 x 2^21 doubles,
+ * 48 MiB), so the call allocates nothing, with or without an earlier
+ * lbm_moments call.  Domains of more than 2^21 nodes (nx*ny) get
+ * LBM_EINVAL.  Every call on one GPU shares that buffer: calls that
+ * overlap on one GPU (different streams, different host threads) race and
+ * must be serialised by the caller; calls on one stream are ordered.  The
+ * copies into rho, ux, uy are enqueued on the domain's stream. */
+int lbm_moments_device_noalloc(lbm_domain *d, double *rho, double *ux, double *uy);
+
 /* Total mass sum over fluid nodes of sum_a f_a at the current time (FP64). */
 int lbm_total_mass(lbm_domain *d, double *out);
 

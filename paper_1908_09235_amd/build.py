@@ -13,6 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 # formulas); the FP32 kernels may fuse multiply-adds.
 UNITS = [("lbm2p.hip", ["-ffp-contract=off"]),
          ("batch.hip", ["-ffp-contract=off"]),
+         ("noalloc.hip", ["-ffp-contract=off"]),
          ("launch_f64.hip", ["-ffp-contract=off"]),
          ("launch_f32.hip", ["-ffp-contract=fast"])]
 DEPS = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [

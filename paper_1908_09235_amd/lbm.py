@@ -74,6 +74,7 @@ EXPORTS = {
     "lbm_sync": (C.c_int, [_H]),
     "lbm_moments": (C.c_int, [_H, _D, _D, _D]),
     "lbm_moments_device": (C.c_int, [_H, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_moments_device_noalloc": (C.c_int, [_H, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_total_mass": (C.c_int, [_H, _D]),
     "lbm_time": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_wall_force": (C.c_int, [_H, _D]),
@@ -223,6 +224,11 @@ def lbm_moments(h, nx, ny):
 
 def lbm_moments_device(h, rho_ptr, ux_ptr, uy_ptr):
     _check(lib().lbm_moments_device(h, rho_ptr, ux_ptr, uy_ptr), "lbm_moments_device")
+
+
+def lbm_moments_device_noalloc(h, rho_ptr, ux_ptr, uy_ptr):
+    _check(lib().lbm_moments_device_noalloc(h, rho_ptr, ux_ptr, uy_ptr),
+           "lbm_moments_device_noalloc")
 
 
 def lbm_total_mass(h):
