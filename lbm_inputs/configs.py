@@ -136,6 +136,38 @@ def static_gravity(q: float, rule="mls", fix="none", nx=100, ny=50, g=0.001,
     return p
 
 
+def sloped_channel(n: int, rule="mls", fix="none", tau=1.0, g0=1e-5, n0=16,
+                   s0=0.35):
+    """Force-driven flow between resting straight walls of slope 1/2 that
+    are not aligned with the lattice: a 2n x n periodic lattice, a solid
+    band s = y - x/2 in [s0, s0 + n/4) (n a multiple of 4, so the wall
+    fractions repeat the same pattern at every n), single phase, rho = 1,
+    body force of magnitude g0 (n0/n)^3 along the walls (diffusive
+    scaling: the same flow in lattice units at every n)."""
+    assert n % 4 == 0
+    band = geo.SlopedBand(n, s0, s0 + n / 4)
+    g = g0 * (n0 / n) ** 3
+    tx, ty = 2.0 / math.sqrt(5.0), 1.0 / math.sqrt(5.0)
+    p = _problem(2 * n, n, [band], np.ones((n, 2 * n)), 1.0, eos="none", tau=tau,
+                 gravity=(g * tx, g * ty), rule=rule, fix=fix, name=f"sloped_channel{n}")
+    p.meta.update(n=n, s0=band.s0, s1=band.s1, g=g, direction=(tx, ty))
+    return p
+
+
+def cylinder_array(d: float, rule="mls", fix="none", tau=1.0, g0=1e-5, d0=8.0):
+    """A periodic square array of resting cylinders of diameter d in cells
+    of 2d x 2d nodes (solid fraction pi/16), exact-circle wall fractions,
+    single phase, rho = 1, body force g0 (d0/d)^3 along x (diffusive
+    scaling)."""
+    L = int(round(2 * d))
+    c = (L - 1) / 2.0
+    g = g0 * (d0 / d) ** 3
+    p = _problem(L, L, [geo.Circle(c, c, d / 2.0)], np.ones((L, L)), 1.0, eos="none",
+                 tau=tau, gravity=(g, 0.0), rule=rule, fix=fix, name=f"cylinder_array{d:g}")
+    p.meta.update(d=d, g=g, cell=L)
+    return p
+
+
 def shear_wave(n: int, U=1e-3, tau=0.8, collision="bgk", mrt_s=None, nx=4):
     """u_x = U sin(2 pi y / n), rho = 1, no walls, no interaction."""
     y = np.arange(n, dtype=np.float64)

@@ -104,6 +104,40 @@ class Band:
         return 0 <= self.y0 < self.y1 <= ny
 
 
+class SlopedBand:
+    """Solid band between two parallel straight walls of slope 1/2 in a
+    periodic nx = 2n by ny = n lattice: a node is solid where
+    s = y - x/2, taken modulo n into [s0, s0 + n), lies in [s0, s1).  The
+    walls are the lines s = s0 (+ n) and s = s1; since s changes by
+    e_y - e_x/2 along a link, the fraction of a cut link is linear in s.
+    The walls are not lattice-aligned, so the fractions vary along them
+    (with the same pattern at every n when s0 and s1 keep their
+    fractional parts)."""
+
+    def __init__(self, n: int, s0: float, s1: float):
+        self.n, self.s0, self.s1 = int(n), float(s0), float(s1)
+
+    def coordinate(self, X, Y):
+        return np.mod(Y - 0.5 * X - self.s0, self.n) + self.s0
+
+    def contains(self, X, Y):
+        s = self.coordinate(X, Y)
+        return (s >= self.s0) & (s < self.s1)
+
+    def fraction(self, xb, yb, ex, ey):
+        s = self.coordinate(xb, yb)          # in [s1, s0 + n) on fluid nodes
+        ds = ey - 0.5 * ex
+        q = np.where(ds > 0, (self.s0 + self.n - s) / np.where(ds > 0, ds, 1.0),
+                     (self.s1 - s) / np.where(ds < 0, ds, -1.0))
+        return np.minimum(q, 1.0)
+
+    def wall_velocity(self, xw, yw):
+        return np.zeros_like(xw), np.zeros_like(yw)
+
+    def fits(self, nx, ny):
+        return nx == 2 * self.n and ny == self.n
+
+
 def build(nx: int, ny: int, shapes: Sequence):
     """Solid mask (uint8 [ny, nx]), owner index per node, and the cut links.
 
