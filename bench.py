@@ -113,37 +113,92 @@ def copy_bandwidth(torch, mib=1024, reps=20):
     return round(2 * (mib << 20) / (ms * 1e-3) / 1e9, 1)
 
 
-def precision_leg(steps, warmup, stream, prof_steps):
+def precision_leg(steps, warmup, stream, prof_steps, check_every, time_steps):
     """Many cylinders with droplets, 8192 x 4096, CS at 0.86 Tc, BGK
-    tau = 0.8, MLS + B: each storage form run from the same start for the
-    same steps; errors of rho and u (max-norm relative, fluid nodes)
-    against the FP64 form."""
+    tau = 0.8, MLS + B.  Accuracy: every storage form advances in lockstep
+    with the FP64 form from the same start, and every check_every steps the
+    max-norm relative errors of rho and u over fluid nodes are taken on the
+    GPU; a form's steps_within_<tol> is the last checked step up to which
+    every check stayed within tol (null if none failed within the run).
+    Rate: each form then times time_steps further steps, and a separate
+    pass of prof_steps gives its mean main-kernel duration."""
     import numpy as np
+    import torch
 
     from lbm_inputs import configs as cfg
+    from paper_1908_09235_amd import lbm
 
     p = cfg.many_cylinders()
-    fl = ~p.solid.astype(bool)
-    out = {"workload": f"{p.name}_bgk_mls_B", "steps": steps}
-    ref = None
-    for st in ("f64", "f32", "f32dev", "f16dev", "f16node"):
-        r = run_gpu(p, st, steps, warmup, stream, 0, 0, prof_steps, moments=True)
-        fluid = r["info"]["fluid_nodes"]
-        rec = {"arith": ARITH[st],
-               "mlups": round(fluid * steps / r["seconds"] / 1e6, 1),
-               "main_kernel_ms": round(r["main_ms"], 5),
+    forms = ("f64", "f32", "f32dev", "f16dev", "f16node")
+    n = p.nx * p.ny
+    fl = torch.from_numpy(~p.solid.astype(bool).reshape(-1)).cuda()
+    doms = {st: lbm.Domain(p, storage=st, stream=stream, history_capacity=1 << 16)
+            for st in forms}
+    fluid = doms["f64"].info()["fluid_nodes"]
+    bufs = {st: torch.empty((3, n), dtype=torch.float64, device="cuda") for st in forms}
+
+    def moments(st):
+        b = bufs[st]
+        lbm.lbm_moments_device(doms[st].h, b[0].data_ptr(), b[1].data_ptr(), b[2].data_ptr())
+
+    tols = (1e-5, 1e-4, 1e-3, 1e-2)
+    within = {st: {t: None for t in tols} for st in forms[1:]}
+    history = {st: [] for st in forms[1:]}
+    m0 = {st: doms[st].total_mass() for st in forms}
+    done = 0
+    while done < steps:
+        k = min(check_every, steps - done)
+        for st in forms:
+            try:
+                doms[st].step(k)
+            except lbm.LbmError:
+                pass  # an unstable form keeps its non-finite fields
+        done += k
+        moments("f64")
+        torch.cuda.synchronize()
+        ref = bufs["f64"][:, fl]
+        den = ref.abs().amax(dim=1)
+        for st in forms[1:]:
+            moments(st)
+            torch.cuda.synchronize()
+            e = ((bufs[st][:, fl] - ref).abs().amax(dim=1) / den).cpu().numpy()
+            e = np.where(np.isfinite(e), e, np.inf)
+            history[st].append((done, float(e[0]), float(e[1]), float(e[2])))
+            for t in tols:
+                if within[st][t] is None and e.max() > t:
+                    within[st][t] = done - k  # the last check that held
+    out = {"workload": f"{p.name}_bgk_mls_B", "steps": steps, "check_every": check_every,
+           "fluid_nodes": fluid}
+    for st in forms:
+        d = doms[st]
+        drift = abs(d.total_mass() - m0[st]) / m0[st]
+        d.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lbm.lbm_step_async(d.h, time_steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        main_ms = 0.0
+        if prof_steps > 0:
+            lbm.lbm_set_profiling(d.h, 1)
+            lbm.lbm_step(d.h, prof_steps)
+            mm, mn, _, _ = lbm.lbm_kernel_times(d.h)
+            lbm.lbm_set_profiling(d.h, 0)
+            main_ms = mm / max(mn, 1)
+        rec = {"arith": ARITH[st], "mlups": round(fluid * time_steps / sec / 1e6, 1),
+               "main_kernel_ms": round(main_ms, 5),
                "main_kernel_gbs": (round((18 * BYTES_PER_POP[st] + EXTRA_BYTES.get(st, 0)) *
-                                         fluid / (r["main_ms"] * 1e-3) / 1e9, 1)
-                                   if r["main_ms"] > 0 else None),
-               "mass_drift": r["drift"]}
-        if st == "f64":
-            ref = r["mom"]
-        else:
-            for i, nm in enumerate(("rho", "ux", "uy")):
-                den = np.max(np.abs(ref[i][fl]))
-                rec[f"err_{nm}"] = float(np.max(np.abs(r["mom"][i][fl] - ref[i][fl])) / den)
+                                         fluid / (main_ms * 1e-3) / 1e9, 1)
+                                   if main_ms > 0 else None),
+               "mass_drift": float(drift)}
+        if st != "f64":
+            last = history[st][-1]
+            rec.update(err_rho=last[1], err_ux=last[2], err_uy=last[3])
+            for t in tols:
+                rec[f"steps_within_{t:g}"] = within[st][t]
+            rec["errors_by_step"] = [[h[0], round(max(h[1:]), 9)] for h in history[st]]
         out[st] = rec
-    out["fluid_nodes"] = fluid
+        d.close()
     return out
 
 
@@ -241,22 +296,16 @@ def rel_err_fields(p, g, ref):
     return out
 
 
-def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
-    """The batched mix: n_inst droplet-on-cylinder instances (sides
-    64..768, T/Tc, tau drawn per instance), one batch, autotuned, each
-    instance run `steps` steps.  Sampled instances are checked against the
-    FP64 plain form; a sample run one by one gives the unbatched rate
-    (alone_steps 0: not measured)."""
+def _batch_run(probs, storage, steps, stream, tune_steps):
+    """One batch of the whole mix: build, tune, run `steps` steps (timed).
+    The batch is returned alive for the read-out."""
     import numpy as np
     import torch
 
-    from lbm_inputs import configs as cfg
     from paper_1908_09235_amd import lbm
 
-    probs = [cfg.batch_instance(k) for k in range(n_inst)]
-    fluid = np.array([p.fluid_nodes for p in probs], dtype=np.float64)
     cap = 1 << int(np.ceil(np.log2(steps + 2)))
-    b = lbm.Batch(storage=storage, eos="cs", max_instances=n_inst, arena_bytes=48 << 30)
+    b = lbm.Batch(storage=storage, eos="cs", max_instances=len(probs), arena_bytes=48 << 30)
     t0 = time.perf_counter()
     slots = [b.add(p, steps, history_capacity=cap) for p in probs]
     t_build = time.perf_counter() - t0
@@ -267,36 +316,62 @@ def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
     t0 = time.perf_counter()
     b.run(steps)
     b.sync()
-    t1 = time.perf_counter()
+    secs = time.perf_counter() - t0
     st = [b.status(s) for s in slots]
     done = np.array([x[0] for x in st], dtype=np.float64) - done0
-    unstable = sum(1 for x in st if x[2] >= 0)
-    secs = t1 - t0
-    lu = float((fluid * done).sum())
-    out = {"workload": f"droplet_cylinder_mix_{n_inst}", "instances": n_inst,
-           "storage": storage, "arith": ARITH[storage], "steps": steps,
-           "nodes": int(sum(p.nx * p.ny for p in probs)),
-           "fluid_nodes": int(fluid.sum()), "seconds": round(secs, 3),
-           "solves_per_s": round(n_inst / secs, 2),
-           "mlups": round(lu / secs / 1e6, 1), "unstable": unstable,
-           "tuned": tuned, "graph_steps": 32, "build_seconds": round(t_build, 2),
-           "info": b.info()}
-    # sampled per-instance error against the FP64 plain form, same steps
+    fluid = np.array([p.fluid_nodes for p in probs], dtype=np.float64)
+    stable = [k for k, x in enumerate(st) if x[2] < 0]
+    rec = {"storage": storage, "arith": ARITH[storage], "seconds": round(secs, 3),
+           "solves_per_s": round(len(stable) / secs, 2),
+           "stable": len(stable), "unstable": len(probs) - len(stable),
+           "mlups": round(float((fluid * done).sum()) / secs / 1e6, 1),
+           "tuned": tuned, "build_seconds": round(t_build, 2), "info": b.info()}
+    return b, slots, st, rec
+
+
+def batch_leg(steps, n_inst, stream, tune_steps, alone_steps, gate=1e-5):
+    """The batched mix: n_inst droplet-on-cylinder instances (sides
+    64..768, T/Tc, tau drawn per instance), one batch each in FP32 and FP64
+    storage, autotuned, each instance run `steps` steps.  A solve is an
+    instance that stays stable for all its steps (the unstable ones stop at
+    their first non-finite mass and are counted apart).  Every instance
+    stable in both is compared with its FP64 run (bit-identical to the
+    plain FP64 form, which the GPU tests check), max-norm relative over
+    fluid nodes; the gated rate is that of the FP64 batch unless every
+    FP32 instance is within the gate.  A sample run one by one gives the
+    unbatched rate (alone_steps 0: not measured)."""
+    import numpy as np
+    import torch
+
+    from lbm_inputs import configs as cfg
+    from paper_1908_09235_amd import lbm
+
+    probs = [cfg.batch_instance(k) for k in range(n_inst)]
+    fluid = np.array([p.fluid_nodes for p in probs], dtype=np.float64)
+    b32, s32, st32, r32 = _batch_run(probs, "f32", steps, stream, tune_steps)
+    b64, s64, st64, r64 = _batch_run(probs, "f64", steps, stream, tune_steps)
     errs = []
-    for k in sample:
-        t_k, _, u_k = st[k]
-        n = int(t_k)
-        g = b.moments(slots[k])
-        with lbm.Domain(probs[k], storage="f64") as d:
-            try:
-                d.step(n)
-            except lbm.LbmError:
-                pass
-            ref = d.moments()
-        errs.append({"instance": k, "side": probs[k].nx, "steps": n, "unstable": u_k,
-                     **rel_err_fields(probs[k], g, ref)})
-    out["sample_vs_fp64"] = errs
-    b.close()
+    for k in range(n_inst):
+        if st32[k][2] >= 0 or st64[k][2] >= 0:
+            continue
+        e = rel_err_fields(probs[k], b32.moments(s32[k]), b64.moments(s64[k]))
+        errs.append((max(e.values()), k, e))
+    b32.close()
+    b64.close()
+    within = sum(1 for m, _, _ in errs if m <= gate)
+    worst = sorted(errs, reverse=True)[:5]
+    both_unstable = sum(1 for k in range(n_inst) if st32[k][2] >= 0 and st64[k][2] >= 0)
+    all_in = within == len(errs)
+    out = {"workload": f"droplet_cylinder_mix_{n_inst}", "instances": n_inst, "steps": steps,
+           "nodes": int(sum(p.nx * p.ny for p in probs)), "fluid_nodes": int(fluid.sum()),
+           "graph_steps": 32, "fp32": r32, "fp64": r64,
+           "vs_fp64": {"gate": gate, "compared": len(errs), "within_gate": within,
+                       "unstable_in_both": both_unstable,
+                       "max_err": max((m for m, _, _ in errs), default=None),
+                       "worst": [{"instance": k, "side": probs[k].nx, **e}
+                                 for _, k, e in worst]},
+           "solves_per_s_at_gate": r32["solves_per_s"] if all_in else r64["solves_per_s"],
+           "storage_at_gate": "f32" if all_in else "f64"}
     if alone_steps <= 0:
         return out
     # the unbatched rate: a sample of instances one after another, one
@@ -304,7 +379,7 @@ def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
     k_alone = list(range(0, n_inst, max(1, n_inst // 16)))
     lu_a, t_a = 0.0, 0.0
     for k in k_alone:
-        with lbm.Domain(probs[k], storage=storage, stream=stream) as d:
+        with lbm.Domain(probs[k], storage="f32", stream=stream) as d:
             d.step(5)
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -316,16 +391,19 @@ def batch_leg(steps, n_inst, storage, stream, tune_steps, sample, alone_steps):
             t_a += time.perf_counter() - ta
             lu_a += fluid[k] * alone_steps
     out["one_by_one_mlups"] = round(lu_a / t_a / 1e6, 1)
-    out["one_by_one_sample"] = f"{len(k_alone)} instances x {alone_steps} steps"
+    out["one_by_one_sample"] = f"{len(k_alone)} instances x {alone_steps} steps, FP32"
     return out
 
 
-def serve_leg(storage, seconds, rates, chunk, pool):
+def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
     """The served workload: Poisson arrivals of droplet-on-cylinder
     requests (95 % the batched mix, 5 % 2048^2; 2000..20000 steps each) into
     one server.  First a saturated run (every request present at t = 0)
-    measures the sustainable completion rate, then the arrival rates in
-    `rates` (fractions of it) give time-to-solution percentiles."""
+    measures the sustainable completion rate of stable solves, then about
+    n_requests arrive at each rate in `rates` (fractions of it) for
+    time-to-solution percentiles.  The first n_check stable requests of the
+    first rate (and its first 2048^2 one) are run again alone in FP64
+    storage and compared (max-norm relative over fluid nodes)."""
     import numpy as np
 
     from lbm_inputs import configs as cfg
@@ -337,10 +415,10 @@ def serve_leg(storage, seconds, rates, chunk, pool):
     e_nodes = 0.95 * np.mean([nodes[k] for k in range(pool)]) + 0.05 * nodes["big"]
     e_steps = 11000.0
 
-    def run(reqs, horizon):
+    def run(reqs, horizon, check=0):
         srv = lbm.Server(chunk_steps=chunk, storage=storage, eos="cs", max_instances=4096,
                          arena_bytes=96 << 30)
-        arrive, done_t, info = {}, {}, {}
+        arrive, done_t, info, fields = {}, {}, {}, {}
         i = 0
         t0 = time.perf_counter()
         lu = 0.0
@@ -354,10 +432,16 @@ def serve_leg(storage, seconds, rates, chunk, pool):
             fin = srv.progress()
             now = time.perf_counter() - t0
             for rid in fin:
-                r = srv.result(rid, fields=False)
                 done_t[rid] = now
+                key = arrive[rid][1]
+                keys = [v[0] for v in fields.values()]
+                want = check > 0 and (("big" not in keys) if key == "big"
+                                      else (len(keys) - keys.count("big") < check))
+                r = srv.result(rid, fields=want)
                 info[rid] = r
-                lu += probs[arrive[rid][1]].fluid_nodes * r["steps"]
+                if want and r["unstable_step"] < 0:
+                    fields[rid] = (key, r["steps"], (r["rho"], r["ux"], r["uy"]))
+                lu += probs[key].fluid_nodes * r["steps"]
                 srv.release(rid)
             if (i == len(reqs) and len(done_t) == len(reqs)) or now > horizon:
                 break
@@ -366,30 +450,44 @@ def serve_leg(storage, seconds, rates, chunk, pool):
         wall = time.perf_counter() - t0
         st = srv.info()
         srv.close()
-        lat = np.array([done_t[r] - arrive[r][0] for r in done_t])
+        ok = [r for r in done_t if info[r]["unstable_step"] < 0]
+        lat = np.array([done_t[r] - arrive[r][0] for r in ok])
         drift = [abs(info[r]["mass"] - info[r]["mass0"]) / info[r]["mass0"]
-                 for r in info if info[r]["unstable_step"] < 0 and np.isfinite(info[r]["mass0"])]
-        return {"requests": len(reqs), "completed": len(done_t), "wall_s": round(wall, 2),
-                "solves_per_s": round(len(done_t) / wall, 2),
-                "mlups": round(lu / wall / 1e6, 1),
-                "p50_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
-                "p99_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
-                "unstable": sum(1 for r in info.values() if r["unstable_step"] >= 0),
-                "max_mass_drift": float(max(drift)) if drift else None,
-                "chunks": st["chunks"], "unfinished": len(reqs) - len(done_t)}
+                 for r in ok if np.isfinite(info[r]["mass0"])]
+        out = {"requests": len(reqs), "completed": len(done_t), "stable": len(ok),
+               "unstable": len(done_t) - len(ok), "wall_s": round(wall, 2),
+               "solves_per_s": round(len(ok) / wall, 2),
+               "mlups": round(lu / wall / 1e6, 1),
+               "p50_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+               "p99_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+               "max_s": round(float(lat.max()), 3) if len(lat) else None,
+               "max_mass_drift": float(max(drift)) if drift else None,
+               "chunks": st["chunks"], "unfinished": len(reqs) - len(done_t)}
+        return out, fields
 
-    # saturated: enough requests for about `seconds` of work at the
-    # batched rate, all present at once
+    # saturated: every request present at once
     sat_reqs = [(0.0, k, s) for (_, k, s) in cfg.request_stream(1000.0, 0.12, pool=pool)]
-    sat = run(sat_reqs, 10 * seconds)
+    sat, _ = run(sat_reqs, 120.0)
     lam_max = sat["solves_per_s"]
     sweep = []
-    for f in rates:
+    for j, f in enumerate(rates):
         lam = max(lam_max * f, 0.1)
-        reqs = cfg.request_stream(lam, seconds, pool=pool)
-        r = run(reqs, 3 * seconds)
+        reqs = cfg.request_stream(lam, n_requests / lam, pool=pool)
+        r, fields = run(reqs, 3 * n_requests / lam + 60, n_check if j == 0 else 0)
         r["rate"] = round(lam, 2)
         r["rate_fraction"] = f
+        if fields:
+            chk = []
+            for rid, (key, steps, g) in fields.items():
+                with lbm.Domain(probs[key], storage="f64") as d:
+                    d.step(steps)
+                    ref = d.moments()
+                chk.append({"request": rid, "instance": key, "steps": steps,
+                            **rel_err_fields(probs[key], g, ref)})
+            r["vs_fp64"] = {"gate": gate, "checked": len(chk),
+                            "within_gate": sum(1 for c in chk if max(
+                                c["err_rho"], c["err_ux"], c["err_uy"]) <= gate),
+                            "requests": chk}
         sweep.append(r)
     offered = 200.0 * e_nodes * e_steps
     return {"workload": "droplet_cylinder_requests", "storage": storage,
@@ -498,13 +596,17 @@ def main():
     ap.add_argument("--oracle-worker", type=float, default=0.0, help=argparse.SUPPRESS)
     ap.add_argument("--precision-steps", type=int, default=2000,
                     help="steps of the 8192 x 4096 precision-form comparison (0: skip)")
+    ap.add_argument("--precision-check", type=int, default=250,
+                    help="steps between the precision forms' error checks")
+    ap.add_argument("--precision-time-steps", type=int, default=500,
+                    help="steps each precision form is timed over")
     ap.add_argument("--batch-steps", type=int, default=5000,
                     help="steps of each instance of the batched mix (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=512)
-    ap.add_argument("--batch-f64", type=int, default=1,
-                    help="also run the batched mix in FP64 storage (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
-                    help="arrival window of each served run (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of each served run at a fixed arrival rate (0: skip)")
+    ap.add_argument("--serve-check", type=int, default=6,
+                    help="served requests compared with an FP64 run of their own")
     ap.add_argument("--serve-chunk", type=int, default=100)
     ap.add_argument("--workloads", type=int, default=1,
                     help="also time the paper's other experiments (0: skip)")
@@ -577,20 +679,16 @@ def main():
 
     prec = None
     if a.precision_steps > 0:
-        prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_steps)
+        prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_steps,
+                             a.precision_check, a.precision_time_steps)
 
     batch = None
     if a.batch_steps > 0:
-        batch = batch_leg(a.batch_steps, a.batch_instances, "f32", stream, 3,
-                          [0, 101, 257, a.batch_instances - 1], 500)
-        if a.batch_f64:
-            # the same mix in FP64 storage: the accuracy gate holds by
-            # construction (the samples must match the plain form exactly)
-            batch["fp64_storage"] = batch_leg(a.batch_steps, a.batch_instances, "f64",
-                                              stream, 3, [0, 257], 0)
+        batch = batch_leg(a.batch_steps, a.batch_instances, stream, 3, 500)
     serve = None
-    if a.serve_seconds > 0:
-        serve = serve_leg("f32", a.serve_seconds, [0.5, 0.8, 1.0], a.serve_chunk, 128)
+    if a.serve_requests > 0:
+        serve = serve_leg("f32", a.serve_requests, [0.5, 0.8], a.serve_chunk, 128,
+                          a.serve_check)
 
     other = workloads_leg(stream) if a.workloads else None
 

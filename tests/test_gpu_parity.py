@@ -417,3 +417,81 @@ def test_scheme_a_negative_rest_population_count(L, case):
     say(f"[gpu] {case}: {steps} steps, negative rest populations {got} (oracle {want})")
     assert got == want
     assert (want == 0) == (case == "cfg1_mls")
+
+
+# ------------------------------------------ schemes A and B on resting walls
+@pytest.mark.parametrize("fix", ["none", "A", "B"])
+@pytest.mark.parametrize("case", ["sloped_channel16", "cylinder_array8"])
+def test_resting_wall_cases_match_oracle(L, case, fix):
+    """The resting-wall convergence cases at their smallest size, MLS with
+    each fix, FP64, 1000 steps: fields and mass history against the
+    oracle.  The body force is 100 times that of the convergence runs, so
+    that the velocities (about 0.03) stand well above the FP64 rounding of
+    the populations in the max-norm of each component."""
+    p = (cfg.sloped_channel(16, fix=fix, g0=1e-3) if case == "sloped_channel16"
+         else cfg.cylinder_array(8.0, fix=fix, g0=1e-3))
+    g = gpu_run(L, p, 1000, history_capacity=2048)
+    compare(p, g, oracle_run(p, 1000, key=(case, fix, "g0=1e-3")), F64_TOL, MASS_TOL)
+
+
+def _sloped_error(p, ux, uy):
+    Y, X = np.mgrid[0:p.ny, 0:p.nx].astype(np.float64)
+    m = p.meta
+    s = geo.SlopedBand(m["n"], m["s0"], m["s1"]).coordinate(X, Y)
+    k = 2.0 / np.sqrt(5.0)
+    z, h = (s - m["s1"]) * k, (m["n"] - (m["s1"] - m["s0"])) * k
+    U = m["g"] / (2.0 * (p.tau - 0.5) / 3.0) * z * (h - z)
+    tx, ty = m["direction"]
+    fl = ~p.solid.astype(bool)
+    return float(np.sqrt((((ux - U * tx) ** 2 + (uy - U * ty) ** 2)[fl]).sum()
+                         / ((U ** 2)[fl]).sum()))
+
+
+@pytest.mark.parametrize("fix", ["none", "A", "B"])
+def test_resting_sloped_walls_convergence_on_gpu(L, fix):
+    """The sloped channel at n = 16 ... 128 in FP64 to steady state: MLS
+    alone converges at second order; A and B at first order, with the
+    total mass constant to round-off (the oracle measures the same orders
+    at n = 16, 32, 48)."""
+    ns = (16, 32, 64, 128)
+    errs, drifts = [], []
+    for n in ns:
+        p = cfg.sloped_channel(n, fix=fix)
+        with L.Domain(p, history_capacity=1 << 10) as d:
+            m0 = d.total_mass()
+            d.step(12 * n * n)
+            _, ux, uy = d.moments()
+            drifts.append(abs(d.total_mass() - m0) / m0)
+        errs.append(_sloped_error(p, ux, uy))
+        say(f"    {fix} n={n}: L2 error {errs[-1]:.4e}, mass change {drifts[-1]:.1e}")
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    say(f"    {fix}: orders {np.round(orders, 3)}")
+    if fix == "none":
+        assert np.all((orders > 1.85) & (orders < 2.2))
+    else:
+        assert np.all((orders > 0.8) & (orders < 1.2))
+        assert max(drifts) < 1e-16 * 12 * ns[-1] ** 2
+
+
+@pytest.mark.parametrize("fix", ["none", "A", "B"])
+def test_resting_cylinder_array_convergence_on_gpu(L, fix):
+    """The cylinder array at d = 8 ... 128 in FP64 to steady state:
+    permeabilities k/d^2, the differences between successive resolutions,
+    and the mass change (reported; A and B to round-off)."""
+    ds = (8.0, 16.0, 32.0, 64.0, 128.0)
+    ks = []
+    for d in ds:
+        p = cfg.cylinder_array(d, fix=fix)
+        with L.Domain(p, history_capacity=1 << 10) as dom:
+            m0 = dom.total_mass()
+            dom.step(int(25 * d * d))
+            _, ux, _ = dom.moments()
+            drift = abs(dom.total_mass() - m0) / m0
+        nu = (p.tau - 0.5) / 3.0
+        ks.append(nu * ux[~p.solid.astype(bool)].sum() / (p.nx * p.ny) / (p.meta["g"] * d * d))
+        say(f"    {fix} d={d:g}: k/d^2 {ks[-1]:.8f}, mass change {drift:.1e}")
+        if fix != "none":
+            assert drift < 1e-16 * 25 * d * d
+    diffs = np.abs(np.diff(ks))
+    say(f"    {fix}: |k(2d) - k(d)| {np.array2string(diffs, precision=3)}")
+    assert diffs[-1] < diffs[0]
