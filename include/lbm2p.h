@@ -244,6 +244,21 @@ int lbm_wall_force(lbm_domain *d, double out[2]);
  * stream. */
 int lbm_negative_rest(lbm_domain *d, int64_t *count);
 
+/* Steps per pass of the main kernel.  With 2, one launch advances two time
+ * steps: the intermediate populations stay in on-chip memory and the wall
+ * rules and corrections of the second step (Eqs. 7-15, 18, 20-23) are
+ * evaluated inside the launch, so the populations cross HBM once per two
+ * updates; the results are bit-identical to single steps.  Available for
+ * the FP32 and FP16-deviation storage forms (not the FP16 per-node one),
+ * periodic domains and every rule but Zhao-Yong (LBM_EINVAL otherwise);
+ * the default is 1.  tile_h is the two-step kernel's rows per workgroup
+ * (0 = default 24, at least 4).  An odd step count ends with a
+ * single step.  After a two-step pass the moments and the wall force of
+ * the last step come from a replay of the intermediate step, in buffers
+ * held since creation. */
+int lbm_set_steps_per_pass(lbm_domain *d, int32_t steps, int32_t tile_h);
+int lbm_get_steps_per_pass(lbm_domain *d, int32_t *steps, int32_t *tile_h);
+
 /* Facts about the built domain: [0] fluid nodes, [1] cut links,
  * [2] boundary nodes, [3] bytes of device memory held, [4] tile_w,
  * [5] tile_h, [6] main-kernel workgroups, [7] boundary-rule fallbacks

@@ -70,6 +70,22 @@ struct lbm_domain {
     double *lc = nullptr, *luw = nullptr;
     long long cap = 0, t = 0;
     long long* clock = nullptr;  // device: step of the last recorded mass
+    // Two steps per pass (k_main2): fused = 2 when in use (1: every step
+    // is its own pass); eligible when the form allows it.
+    int fused = 1;
+    bool fusable = false;
+    int tile_h2 = 0, nstrips2 = 0, nsegs2 = 0, nblocks2 = 0;
+    int* node_link = nullptr;    // per node (pitch layout): first link slot + 1, or 0
+    double* partial2 = nullptr;  // masses of the second step of a pass
+    int pending_steps = 0;       // steps of the last pass whose masses are pending
+    // After a two-step pass f*(t - 1) is not in memory: the buffer that
+    // held f*(t - 2) still does, with the ghosts of step t - 1, and the
+    // moments at t and the wall force of the last step are read from a
+    // replay of step t - 1 into these buffers.
+    bool last_fused = false;
+    bool replay_valid = false;
+    void* frep = nullptr;
+    double* side_mom_rep = nullptr;
     bool pending = false;
     long long pending_t = 0;
     hipStream_t stream = nullptr;
@@ -106,5 +122,10 @@ void domain_free(lbm_domain* d);
 // most partial_cap tiles); the next launch uses it.
 int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h);
 Ctx domain_ctx(lbm_domain* d);
+// The buffer the moments at the current time are pulled from: f*(t - 1)
+// with the ghosts of step t (after a two-step pass, rebuilt by a replay of
+// step t - 1 into the domain's replay buffer; also forms the wall force of
+// the last step).  Enqueued on the domain's stream; allocates nothing.
+const void* moments_source(lbm_domain* d);
 
 }  // namespace lbm

@@ -126,6 +126,35 @@ struct RowLoad {
     float pw;      // FP16 storage: psi_w of a solid node in FP32
 };
 
+// Density, force and velocity of one node from its pulled populations fc
+// (stored form: f, or with DEV 1 the deviations from w rho_ref) and the
+// psi of the node and its neighbours ps[a] = psi(x + e_a):
+//   rho = sum f (Eq. 5); F = -G psi(x) sum_a w_a psi(x + e_a) e_a (Eq. 16),
+//   opposite neighbours paired, plus rho g; u = (sum f e + F/2) / rho (Eq. 5).
+template <typename R, int EOS, int DEV>
+__device__ __forceinline__ void node_moments(const R fc[9], const R ps[9], const Phys<R>& ph,
+                                             R& rho, R& drho, R& ux, R& uy, R& Fx, R& Fy) {
+    drho = dens<R>(fc);
+    rho = DEV == 1 ? ph.rref + drho : drho;
+    const R irho = rcp(rho);
+    Fx = R(0);
+    Fy = R(0);
+    if constexpr (EOS != EOS_NONE) {
+        const R w1 = R(wf(1)), w5 = R(wf(5));
+        const R sx = w1 * (ps[1] - ps[3]) + w5 * ((ps[5] - ps[7]) + (ps[8] - ps[6]));
+        const R sy = w1 * (ps[2] - ps[4]) + w5 * ((ps[5] - ps[7]) + (ps[6] - ps[8]));
+        const R g = -ph.G * ps[0];
+        Fx = g * sx;
+        Fy = g * sy;
+    }
+    Fx += rho * ph.gx;
+    Fy += rho * ph.gy;
+    const R mx = (fc[1] - fc[3]) + ((fc[5] - fc[7]) + (fc[8] - fc[6]));
+    const R my = (fc[2] - fc[4]) + ((fc[5] - fc[7]) + (fc[6] - fc[8]));
+    ux = (mx + R(0.5) * Fx) * irho;
+    uy = (my + R(0.5) * Fy) * irho;
+}
+
 // Columns a strip updates: a workgroup of tile_w lanes also pulls the
 // column on either side of its strip, for psi only.
 __host__ __device__ constexpr int strip_cols(int tile_w) { return tile_w - 2; }
@@ -316,32 +345,13 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         R fc[9];  // f, or (DEV 1) the deviations g
         decode(Lc, rr, fc);
         const int c = tid;
-        const R drho = dens<R>(fc);
-        const R rho = DEV == 1 ? ph.rref + drho : drho;
-        const R irho = rcp(rho);
-        R Fx = R(0), Fy = R(0);
-        if constexpr (EOS != EOS_NONE) {
-            // Eq. (16): F = -G psi(x) sum_a w_a psi(x + e_a) e_a, with
-            // opposite neighbours paired
-            const int cl = c > 0 ? c - 1 : 0, cr = c < W - 1 ? c + 1 : W - 1;
-            const R p1 = ring[s0][cr], p3 = ring[s0][cl];
-            const R p2 = ring[syp][c], p4 = ring[sym][c];
-            const R p5 = ring[syp][cr], p6 = ring[syp][cl];
-            const R p7 = ring[sym][cl], p8 = ring[sym][cr];
-            const R w1 = R(wf(1)), w5 = R(wf(5));
-            const R sx = w1 * (p1 - p3) + w5 * ((p5 - p7) + (p8 - p6));
-            const R sy = w1 * (p2 - p4) + w5 * ((p5 - p7) + (p6 - p8));
-            const R g = -ph.G * ring[s0][c];
-            Fx = g * sx;
-            Fy = g * sy;
-        }
-        Fx += rho * ph.gx;
-        Fy += rho * ph.gy;
-        // Eq. (5)
-        const R mx = (fc[1] - fc[3]) + ((fc[5] - fc[7]) + (fc[8] - fc[6]));
-        const R my = (fc[2] - fc[4]) + ((fc[5] - fc[7]) + (fc[6] - fc[8]));
-        const R ux = (mx + R(0.5) * Fx) * irho;
-        const R uy = (my + R(0.5) * Fy) * irho;
+        // psi of the node and of its eight neighbours, by direction
+        const int cl = c > 0 ? c - 1 : 0, cr = c < W - 1 ? c + 1 : W - 1;
+        const R ps[9] = {ring[s0][c],    ring[s0][cr],   ring[syp][c],
+                         ring[s0][cl],   ring[sym][c],   ring[syp][cr],
+                         ring[syp][cl],  ring[sym][cl],  ring[sym][cr]};
+        R rho, drho, ux, uy, Fx, Fy;
+        node_moments<R, EOS, DEV>(fc, ps, ph, rho, drho, ux, uy, Fx, Fy);
         if constexpr (MOMENTS) {
             if (upd && k < H) {
                 const bool fl = live;
@@ -504,11 +514,25 @@ __device__ __forceinline__ void reduce_on_clock(const double* __restrict__ parti
     }
 }
 
-template <int Unused = 0>
-__global__ __launch_bounds__(256) void k_reduce(const double* partial, int np,
-                                                double* hist, long long cap,
-                                                long long* clock, long long* unstable) {
+// The masses of the last pass: one step (partial2 null) or two steps per
+// pass (partial, then partial2), each recorded at the next step of the clock.
+__device__ __forceinline__ void reduce_pass(const double* __restrict__ partial,
+                                            const double* __restrict__ partial2, int np,
+                                            double* __restrict__ hist, long long cap,
+                                            long long* __restrict__ clock,
+                                            long long* __restrict__ unstable) {
     reduce_on_clock(partial, np, hist, cap, clock, unstable);
+    if (partial2) {
+        __syncthreads();  // every thread has read the first total
+        reduce_on_clock(partial2, np, hist, cap, clock, unstable);
+    }
+}
+
+template <int Unused = 0>
+__global__ __launch_bounds__(256) void k_reduce(const double* partial, const double* partial2,
+                                                int np, double* hist, long long cap,
+                                                long long* clock, long long* unstable) {
+    reduce_pass(partial, partial2, np, hist, cap, clock, unstable);
 }
 
 // ---------------------------------------------------------------- boundary
@@ -547,8 +571,10 @@ struct BndArgs {
     const int* __restrict__ lref;    // DEV 2: side slot whose density encodes
                                      // the ghost (one boundary node per ghost)
     int fix;                         // 0 none, 1 A, 2 B, 3 Bao
-    // reduction of the previous main launch's mass partials (last block)
+    // reduction of the previous main launch's mass partials (last block):
+    // one array per step of that launch (partial2 null for a single step)
     const double* __restrict__ partial;
+    const double* __restrict__ partial2;
     int np;
     double* __restrict__ hist;
     long long cap;                   // history ring entries
@@ -570,6 +596,56 @@ struct BndArgs {
 };
 
 constexpr int LK_PAD = 15;
+
+// Inputs of a wall rule besides f*_a(x_b) and the node's own moments,
+// fetched only by the kinds that use them.
+enum : int { LV_OD_B, LV_D_F, LV_D_FF, LV_OD_F, LV_PRE, LV_UFX, LV_UFY };
+
+// The incoming population f_abar(x_b, t + 1) of one cut link (x_b, a) from
+// its kind and coefficients c (table layout of BndArgs::lc), the wall
+// velocity uw, f*_a(x_b, t) = fab and the node's moments rho_b, u_b;
+// fetch(LV_*) supplies the other populations and u_f.  Also returns chi
+// (ch), the bracket of Eq. (8) (bk) and the moving-wall term (wl), which
+// schemes A and B need.  The one evaluation of every rule: both the
+// boundary pass and the two-steps-per-pass kernel call it, so both round
+// every rule alike.
+template <typename F>
+__device__ __forceinline__ double link_value(int kind, int d, const double* c, double uwx,
+                                             double uwy, double fab, double rho_b, double ubx,
+                                             double uby, double& ch, double& bk, double& wl,
+                                             F&& fetch) {
+    const double ex = double(cx(d)), ey = double(cy(d));
+    // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
+    wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
+    ch = 0.0;
+    bk = 0.0;
+    if (kind == LK_HALFWAY) return fab - wl;
+    if (kind <= LK_CHI_EXT) {
+        double usx, usy;
+        if (kind == LK_CHI_UB) {
+            usx = ubx;
+            usy = uby;
+        } else if (kind == LK_CHI_UF) {
+            usx = fetch(LV_UFX);
+            usy = fetch(LV_UFY);
+        } else {
+            usx = c[4] * ubx + c[5];
+            usy = c[4] * uby + c[6];
+        }
+        ch = c[3];
+        // Eq. (8): w_a [1 + 3 e.u_s + 4.5 (e.u_b)^2 - 1.5 u_b^2]
+        const double eus = edot<double>(d, usx, usy);
+        const double eub = edot<double>(d, ubx, uby);
+        const double ub2 = ubx * ubx + uby * uby;
+        bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
+        return (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
+    }
+    if (kind == LK_LIN_F) return c[0] * fab + c[1] * fetch(LV_D_F);
+    if (kind == LK_LIN_B) return c[0] * fab + c[1] * fetch(LV_OD_B);
+    if (kind == LK_QUAD_F) return c[0] * fab + c[1] * fetch(LV_D_F) - c[2] * fetch(LV_D_FF);
+    if (kind == LK_QUAD_B) return c[0] * fab + c[1] * fetch(LV_OD_B) - c[2] * fetch(LV_OD_F);
+    return c[0] * fetch(LV_OD_B) + c[1] * fetch(LV_PRE);  // LK_ZY, Eq. (14)
+}
 
 // Block `blk` of 256 link slots.
 template <typename S, int DEV>
@@ -607,44 +683,19 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
         node = node_r;
         const int od = opp(d);
         const double* mom = b.side_mom + 3 * slotb;
-        const double rho_b = mom[0], ubx = mom[1], uby = mom[2];
-        const double ex = double(cx(d)), ey = double(cy(d));
         fab = ld(d, node);
-        // momentum of a moving wall, Ladd / Mei et al.: 2 w_a rho_b e.u_w / c_s^2
-        wl = 2.0 * wt(d) * rho_b * 3.0 * (ex * uwx + ey * uwy);
-        if (kind == LK_HALFWAY) {
-            r = fab - wl;
-        } else if (kind <= LK_CHI_EXT) {
-            double usx, usy;
-            if (kind == LK_CHI_UB) {
-                usx = ubx;
-                usy = uby;
-            } else if (kind == LK_CHI_UF) {
-                const double* mf = b.side_mom + 3 * slotf;
-                usx = mf[1];
-                usy = mf[2];
-            } else {
-                usx = c[4] * ubx + c[5];
-                usy = c[4] * uby + c[6];
-            }
-            ch = c[3];
-            // Eq. (8): w_a [1 + 3 e.u_s + 4.5 (e.u_b)^2 - 1.5 u_b^2]
-            const double eus = edot<double>(d, usx, usy);
-            const double eub = edot<double>(d, ubx, uby);
-            const double ub2 = ubx * ubx + uby * uby;
-            bk = wt(d) * (1.0 + 3.0 * eus + 4.5 * (eub * eub) - 1.5 * ub2);
-            r = (1.0 - ch) * fab + ch * (rho_b * bk) - wl;  // Eq. (7)
-        } else if (kind == LK_LIN_F) {
-            r = c[0] * fab + c[1] * ld(d, xf);
-        } else if (kind == LK_LIN_B) {
-            r = c[0] * fab + c[1] * ld(od, node);
-        } else if (kind == LK_QUAD_F) {
-            r = c[0] * fab + c[1] * ld(d, xf) - c[2] * ld(d, xff);
-        } else if (kind == LK_QUAD_B) {
-            r = c[0] * fab + c[1] * ld(od, node) - c[2] * ld(od, xf);
-        } else {  // LK_ZY, Eq. (14)
-            r = c[0] * ld(od, node) + c[1] * b.side_f[9 * slotb + d];
-        }
+        r = link_value(kind, d, c, uwx, uwy, fab, mom[0], mom[1], mom[2], ch, bk, wl,
+                       [&](int what) -> double {
+                           switch (what) {
+                           case LV_OD_B: return ld(od, node);
+                           case LV_D_F: return ld(d, xf);
+                           case LV_D_FF: return ld(d, xff);
+                           case LV_OD_F: return ld(od, xf);
+                           case LV_PRE: return b.side_f[9 * slotb + d];
+                           case LV_UFX: return b.side_mom[3 * slotf + 1];
+                           default: return b.side_mom[3 * slotf + 2];
+                           }
+                       });
     }
     s_fab[tid] = fab;
     s_inc[tid] = r;
@@ -782,7 +833,7 @@ __device__ __forceinline__ void open_rows(S* __restrict__ A, const BndArgs& b, i
 template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary(S* __restrict__ A, BndArgs b) {
     if (blockIdx.x == gridDim.x - 1) {
-        if (b.do_reduce) reduce_on_clock(b.partial, b.np, b.hist, b.cap, b.clock, b.unstable);
+        if (b.do_reduce) reduce_pass(b.partial, b.partial2, b.np, b.hist, b.cap, b.clock, b.unstable);
         return;
     }
     if (int(blockIdx.x) >= b.nlink_blocks) {
@@ -993,6 +1044,7 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.lref = I.lref;
         a.fix = I.fix;
         a.partial = nullptr;
+        a.partial2 = nullptr;
         a.np = 0;
         a.hist = nullptr;
         a.cap = 1;

@@ -5,7 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "kernels.hpp"
+#include "fused.hpp"
 
 namespace lbm {
 
@@ -27,11 +27,23 @@ struct Ctx {
     const float* ref;  // init: density plane of the buffer being filled (or null)
     Phys<double> ph;  // converted to the compute type by the launcher
     hipStream_t stream;
+    // two steps per pass (k_main2)
+    int tile_h2, nsegs2, nstrips2, nblocks2;
+    const int* node_link;
+    double* partial2;
+    const int* lmeta;
+    const double* lc;
+    const double* luw;
+    unsigned long long* negrest;
+    int fix;
 };
 
 // one main pass src -> dst (or the moments of src when moments is set)
 void launch_main_f64(const Ctx& c, const void* src, void* dst, bool moments);
 void launch_main_f32(const Ctx& c, const void* src, void* dst, bool moments);
+// two steps per pass src -> dst (storage forms with FP32 or FP16
+// populations and one reference density; see fused.hpp)
+void launch_main2_f32(const Ctx& c, const void* src, void* dst);
 // one boundary pass on cur
 void launch_boundary_f64(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
 void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks);
@@ -41,8 +53,9 @@ void launch_init_f64(const Ctx& c, const double* rho_wall, const double* rho0,
                      const double* ux0, const double* uy0, void* buf, void* other);
 void launch_init_f32(const Ctx& c, const double* rho_wall, const double* rho0,
                      const double* ux0, const double* uy0, void* buf, void* other);
-// the main pass's partials into hist[(clock + 1) % cap]; clock += 1
-void launch_reduce(const Ctx& c, long long cap, long long* clock, double* hist,
+// the last main pass's partials (two arrays if it made two steps) into
+// hist[(clock + 1) % cap], clock += 1 per step
+void launch_reduce(const Ctx& c, bool two, long long cap, long long* clock, double* hist,
                    long long* unstable);
 
 // One step of a batch: boundary and main passes (per storage precision),

@@ -1,8 +1,11 @@
 // FP32 storage with FP64 arithmetic (LBM_STORE_F32) or FP32 arithmetic
 // (LBM_STORE_F32_ARITH32); FP32 or FP16 deviations g = f - w rho_ref with
 // FP32 arithmetic (LBM_STORE_F32DEV, LBM_STORE_F16DEV); FP16 deviations
-// from a per-node reference (LBM_STORE_F16NODE).  Built with fused
-// multiply-adds allowed.
+// from a per-node reference (LBM_STORE_F16NODE).  Built with
+// -ffp-contract=off: every product and sum rounds as written (the FP16
+// per-node decode fuses its multiply-adds explicitly), so that a kernel's
+// arithmetic does not depend on what the compiler would contract where,
+// and the two-steps-per-pass kernel rounds exactly as two single steps.
 #include "launch_impl.hpp"
 
 namespace lbm {
@@ -14,6 +17,14 @@ void launch_main_f32(const Ctx& c, const void* src, void* dst, bool moments) {
     case 4: main_any<_Float16, float, 1>(c, src, dst, moments); break;
     case 5: main_any<_Float16, float, 2>(c, src, dst, moments); break;
     default: main_any<float, double>(c, src, dst, moments);
+    }
+}
+void launch_main2_f32(const Ctx& c, const void* src, void* dst) {
+    switch (c.storage) {
+    case 2: main2_any<float, float, 0>(c, src, dst); break;
+    case 3: main2_any<float, float, 1>(c, src, dst); break;
+    case 4: main2_any<_Float16, float, 1>(c, src, dst); break;
+    default: main2_any<float, double, 0>(c, src, dst);
     }
 }
 void launch_boundary_f32(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {

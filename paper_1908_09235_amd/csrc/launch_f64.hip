@@ -14,10 +14,11 @@ void launch_init_f64(const Ctx& c, const double* rw, const double* r0, const dou
                      const double* v0, void* buf, void* other) {
     init_any<double, double>(c, rw, r0, u0, v0, buf, other);
 }
-void launch_reduce(const Ctx& c, long long cap, long long* clock, double* hist,
+void launch_reduce(const Ctx& c, bool two, long long cap, long long* clock, double* hist,
                    long long* unstable) {
-    hipLaunchKernelGGL(k_reduce<0>, dim3(1), dim3(256), 0, c.stream, c.partial, c.nblocks,
-                       hist, cap, clock, unstable);
+    hipLaunchKernelGGL(k_reduce<0>, dim3(1), dim3(256), 0, c.stream, c.partial,
+                       two ? c.partial2 : nullptr, two ? c.nblocks2 : c.nblocks, hist, cap,
+                       clock, unstable);
 }
 
 void launch_batch_f64(const BatchLaunch& L) { batch_any<double, double, 0>(L); }

@@ -51,6 +51,44 @@ void main_any(const Ctx& c, const void* src, void* dst, bool moments) {
     else main_e<S, R, false, DEV, false>(c, s, t);
 }
 
+template <typename S, typename R, int EOS, int DEV>
+void main2_t(const Ctx& c, const S* src, S* dst) {
+    Main2Args<S> a{};
+    a.src = src;
+    a.dst = dst;
+    a.flags = c.flags;
+    a.side_idx = c.side_idx;
+    a.node_link = c.node_link;
+    a.psiw = c.psiw;
+    a.side_mom = c.side_mom;
+    a.partial1 = c.partial;
+    a.partial2 = c.partial2;
+    a.lmeta = c.lmeta;
+    a.lc = c.lc;
+    a.luw = c.luw;
+    a.negrest = c.negrest;
+    a.fix = c.fix;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.pitch = c.pitch;
+    a.plane = c.plane;
+    a.tile_h = c.tile_h2;
+    a.nsegs = c.nsegs2;
+    a.nstrips = c.nstrips2;
+    a.side_mom_bytes = c.side_mom_bytes;
+    hipLaunchKernelGGL((k_main2<S, R, EOS, DEV>), dim3(c.nblocks2), dim3(kF2Lanes), 0, c.stream,
+                       a, convert<R>(c.ph));
+}
+
+template <typename S, typename R, int DEV>
+void main2_any(const Ctx& c, const void* src, void* dst) {
+    const S* s = static_cast<const S*>(src);
+    S* t = static_cast<S*>(dst);
+    if (c.eos == EOS_NONE) main2_t<S, R, EOS_NONE, DEV>(c, s, t);
+    else if (c.eos == EOS_EXP) main2_t<S, R, EOS_EXP, DEV>(c, s, t);
+    else main2_t<S, R, EOS_CS, DEV>(c, s, t);
+}
+
 template <typename S, int DEV = 0>
 void boundary_any(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
     hipLaunchKernelGGL((k_boundary<S, DEV>), dim3(nblocks), dim3(256), 0, c.stream,

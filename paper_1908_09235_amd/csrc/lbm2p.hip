@@ -19,6 +19,8 @@ namespace {
 
 constexpr uint64_t kStateMagic = 0x6c626d3270737431ULL;  // "lbm2pst1"
 constexpr int kProfPool = 1024;
+constexpr int kTileH2 = 24;     // rows per segment of the two-step kernel
+constexpr int kMinTileH2 = 4;
 
 }  // namespace
 
@@ -153,6 +155,17 @@ Ctx ctx(lbm_domain* d) {
     c.ref = nullptr;
     c.ph = d->ph64;
     c.stream = d->stream;
+    c.tile_h2 = d->tile_h2;
+    c.nsegs2 = d->nsegs2;
+    c.nstrips2 = d->nstrips2;
+    c.nblocks2 = d->nblocks2;
+    c.node_link = d->node_link;
+    c.partial2 = d->partial2;
+    c.lmeta = d->lmeta;
+    c.lc = d->lc;
+    c.luw = d->luw;
+    c.negrest = d->negrest;
+    c.fix = d->fix;
     return c;
 }
 
@@ -182,7 +195,8 @@ BndArgs bnd_args(lbm_domain* d) {
     b.lref = d->lref;
     b.fix = d->fix;
     b.partial = d->partial;
-    b.np = d->nblocks;
+    b.partial2 = d->pending_steps == 2 ? d->partial2 : nullptr;
+    b.np = d->pending_steps == 2 ? d->nblocks2 : d->nblocks;
     b.hist = d->hist;
     b.unstable = d->unstable;
     b.do_reduce = d->pending ? 1 : 0;
@@ -211,7 +225,7 @@ void launch_boundary(lbm_domain* d, void* cur) {
 
 void reduce_pending(lbm_domain* d) {
     if (!d->pending) return;
-    launch_reduce(ctx(d), d->cap, d->clock, d->hist, d->unstable);
+    launch_reduce(ctx(d), d->pending_steps == 2, d->cap, d->clock, d->hist, d->unstable);
     d->pending = false;
 }
 
@@ -242,45 +256,63 @@ int harvest(lbm_domain* d) {
     return LBM_OK;
 }
 
-// One step as plain launches: boundary pass on f*(t) (which also records
-// the previous step's mass), main pass f*(t) -> f*(t + 1).  With rec, HIP
-// events bracket both launches.
-void launch_step(lbm_domain* d, hipEvent_t* rec) {
+// One pass as plain launches: boundary pass on f*(t) (which also records
+// the masses of the previous pass), then the main pass f*(t) -> f*(t + 1),
+// or with two = true f*(t) -> f*(t + 2).  With rec, HIP events bracket
+// both launches.
+void launch_pass(lbm_domain* d, bool two, hipEvent_t* rec) {
     void* cur = d->f[d->cur];
     void* nxt = d->f[d->cur ^ 1];
     if (rec) (void)hipEventRecord(rec[0], d->stream);
     launch_boundary(d, cur);
     if (rec) (void)hipEventRecord(rec[1], d->stream);
     if (rec) (void)hipEventRecord(rec[2], d->stream);
-    launch_main(d, cur, nxt, false);
+    if (two) launch_main2_f32(ctx(d), cur, nxt);
+    else launch_main(d, cur, nxt, false);
     if (rec) (void)hipEventRecord(rec[3], d->stream);
     d->cur ^= 1;
-    d->t += 1;
+    d->t += two ? 2 : 1;
     d->pending = true;
+    d->pending_steps = two ? 2 : 1;
     d->pending_t = d->t;
+    d->last_fused = two;
+    d->replay_valid = false;
 }
 
-// Steps with kernel timing: plain launches, events on every prof-th step.
-// (the caller has reduced any pending mass)
-int run_steps_profiled(lbm_domain* d, int64_t n) {
-    for (int64_t i = 0; i < n; ++i) {
-        const bool rec = (d->t % d->prof) == 0;
-        if (rec && d->nrec == kProfPool) {
-            int rc = harvest(d);
-            if (rc) return rc;
-        }
-        launch_step(d, rec ? &d->ev[4 * d->nrec] : nullptr);
-        if (rec) d->nrec++;
+// The passes of n steps: two steps each when the domain fuses them, with
+// a single step last if n is odd.
+template <typename F>
+void for_passes(const lbm_domain* d, int64_t n, F&& pass) {
+    for (int64_t i = 0; i < n;) {
+        const bool two = d->fused == 2 && n - i >= 2;
+        pass(two);
+        i += two ? 2 : 1;
     }
+}
+
+// Steps with kernel timing: plain launches, events on the passes that
+// start at a multiple of prof steps.  (The caller has reduced any pending
+// mass.)
+int run_steps_profiled(lbm_domain* d, int64_t n) {
+    int rc = LBM_OK;
+    for_passes(d, n, [&](bool two) {
+        if (rc) return;
+        const bool rec = (d->t % d->prof) == 0 || (two && ((d->t + 1) % d->prof) == 0);
+        if (rec && d->nrec == kProfPool) rc = harvest(d);
+        if (rc) return;
+        launch_pass(d, two, rec ? &d->ev[4 * d->nrec] : nullptr);
+        if (rec) d->nrec++;
+    });
+    if (rc) return rc;
     reduce_pending(d);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 
 // The graph of 2^level steps that starts with f*(t) in buffer `parity`:
-// the steps' launches and the closing reduction, captured on the domain's
-// capture stream (the kernels only read the step from the device clock,
-// so every replay continues where the last one stopped).  Null if capture
-// is not available.
+// the passes' launches and the closing reduction, captured on the
+// domain's capture stream (the kernels only read the step from the device
+// clock, so every replay continues where the last one stopped).  Null if
+// capture is not available.
 hipGraphExec_t step_graph(lbm_domain* d, int parity, int level) {
     hipGraphExec_t& g = d->graphs[parity][level];
     if (g || d->graphs_off) return g;
@@ -292,9 +324,9 @@ hipGraphExec_t step_graph(lbm_domain* d, int parity, int level) {
         return nullptr;
     }
     // replay the bookkeeping of plain launches on a copy of the host state
-    const int cur0 = d->cur;
+    const int cur0 = d->cur, ps0 = d->pending_steps;
     const long long t0 = d->t, pt0 = d->pending_t;
-    const bool p0 = d->pending;
+    const bool p0 = d->pending, lf0 = d->last_fused, rv0 = d->replay_valid;
     const hipStream_t s0 = d->stream;
     d->cur = parity;
     d->pending = false;
@@ -302,7 +334,7 @@ hipGraphExec_t step_graph(lbm_domain* d, int parity, int level) {
     hipGraph_t graph = nullptr;
     bool ok = hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-        for (int k = 0; k < (1 << level); ++k) launch_step(d, nullptr);
+        for_passes(d, 1LL << level, [&](bool two) { launch_pass(d, two, nullptr); });
         reduce_pending(d);
         ok = hipStreamEndCapture(d->stream, &graph) == hipSuccess && graph;
     }
@@ -311,7 +343,10 @@ hipGraphExec_t step_graph(lbm_domain* d, int parity, int level) {
     d->cur = cur0;
     d->t = t0;
     d->pending = p0;
+    d->pending_steps = ps0;
     d->pending_t = pt0;
+    d->last_fused = lf0;
+    d->replay_valid = rv0;
     d->stream = s0;
     if (!ok) {
         g = nullptr;
@@ -339,11 +374,16 @@ int run_steps(lbm_domain* d, int64_t n) {
         hipGraphExec_t g = d->graphs_off ? nullptr : d->graphs[d->cur][level];
         if (g) {
             if (hipGraphLaunch(g, d->stream) != hipSuccess) return LBM_EDEVICE;
-            d->cur ^= (int)(k & 1);
-            d->t += k;
+            // the bookkeeping the captured passes did
+            for_passes(d, k, [&](bool two) {
+                d->cur ^= 1;
+                d->t += two ? 2 : 1;
+                d->last_fused = two;
+            });
             d->pending_t = d->t;
+            d->replay_valid = false;
         } else {
-            for (long long i = 0; i < k; ++i) launch_step(d, nullptr);
+            for_passes(d, k, [&](bool two) { launch_pass(d, two, nullptr); });
             reduce_pending(d);
         }
         n -= k;
@@ -504,6 +544,18 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->nstrips = (nx + strip_cols(d->tile_w) - 1) / strip_cols(d->tile_w);
     d->nsegs = (ny + d->tile_h - 1) / d->tile_h;
     d->nblocks = d->nstrips * d->nsegs;
+    // two steps per pass: FP32 or FP16 populations with one reference
+    // density, periodic, any rule but Zhao-Yong (which needs the
+    // pre-collision populations of the intermediate step); not for the
+    // instances of a batch, which run the batched kernels
+    d->fusable = (s->storage == LBM_STORE_F32 || s->storage == LBM_STORE_F32_ARITH32 ||
+                  s->storage == LBM_STORE_F32DEV || s->storage == LBM_STORE_F16DEV) &&
+                 !s->open_x && s->rule != LBM_RULE_ZHAO_YONG && !d->arena;
+    d->fused = 1;  // two steps per pass on request (lbm_set_steps_per_pass)
+    d->tile_h2 = kTileH2;
+    d->nstrips2 = (nx + kF2Cols - 1) / kF2Cols;
+    d->nsegs2 = (ny + d->tile_h2 - 1) / d->tile_h2;
+    d->nblocks2 = d->nstrips2 * d->nsegs2;
     d->cap = s->history_capacity > 0 ? s->history_capacity : (1LL << 20);
     d->stream = static_cast<hipStream_t>(s->stream);
     const int P = d->pitch;
@@ -512,6 +564,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     // ---- boundary tables
     std::vector<uint8_t> flags((size_t)P * ny, 0);
     std::vector<int> side_idx((size_t)P * ny, -1);
+    std::vector<int> node_link((size_t)P * ny, 0);  // first link slot + 1 of a boundary node
     for (long long i = 0; i < N; ++i)
         if (solid(i)) flags[pidx((int)(i % nx), (int)(i / nx))] |= FL_SOLID;
     d->save_f = s->rule == LBM_RULE_ZHAO_YONG;
@@ -550,6 +603,7 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         if (used + len > 256) pad_to(lnode.size() + (256 - used));
         const int x = recs[k0].node % nx, y = recs[k0].node / nx;
         const int sb = slot_of(x, y);
+        node_link[pidx(x, y)] = (int)lnode.size() + 1;
         if (d->save_f) flags[pidx(x, y)] |= FL_SAVE_F;
         ++nb;
         for (long long k = k0; k < k1; ++k) {
@@ -687,7 +741,20 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         return rc;
     // partials for any tile shape down to 64 x 8 (the batched form retunes)
     d->partial_cap = std::max(d->nblocks, ((nx + strip_cols(64) - 1) / strip_cols(64)) * ((ny + 7) / 8));
+    if (d->fusable)  // and for two-step tiles down to kMinTileH2 rows
+        d->partial_cap = std::max(d->partial_cap,
+                                  d->nstrips2 * ((ny + kMinTileH2 - 1) / kMinTileH2));
     if ((rc = dev_alloc(d, (void**)&d->partial, (size_t)d->partial_cap * 8))) return rc;
+    if (d->fusable) {
+        if ((rc = dev_alloc(d, (void**)&d->partial2, (size_t)d->partial_cap * 8))) return rc;
+        if ((rc = upload(d, &d->node_link, node_link))) return rc;
+        // the replay of the intermediate step (moments and wall force after
+        // a two-step pass), held from the start so that reading them never
+        // allocates
+        if ((rc = dev_alloc(d, &d->frep, fbytes))) return rc;
+        if ((rc = dev_alloc(d, (void**)&d->side_mom_rep, (size_t)3 * std::max(nslots, 1) * 8)))
+            return rc;
+    }
     if ((rc = dev_alloc(d, (void**)&d->hist, (size_t)d->cap * 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->unstable, 8))) return rc;
     if ((rc = dev_alloc(d, (void**)&d->clock, 8))) return rc;
@@ -747,6 +814,11 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         launch_init_f32(c, drw, dr0, du0, dv0, d->f[1], d->f[0]);
     }
     launch_main(d, d->f[1], d->f[0], false);
+    // the replay buffer starts as a copy, so that its solid nodes hold
+    // psi of the wall density in their rest slots as the state buffers do
+    if (d->frep && hipMemcpyAsync(d->frep, d->f[0], d->fbytes, hipMemcpyDeviceToDevice,
+                                  d->stream) != hipSuccess)
+        return LBM_EDEVICE;
     d->cur = 0;
     d->t = 0;
     d->pending = true;
@@ -797,6 +869,26 @@ int domain_set_tiles(lbm_domain* d, int tile_w, int tile_h) {
 }
 
 Ctx domain_ctx(lbm_domain* d) { return ctx(d); }
+
+const void* moments_source(lbm_domain* d) {
+    if (!d->last_fused) return d->f[d->cur ^ 1];
+    if (!d->replay_valid) {
+        // step t - 1 from f*(t - 2), whose ghosts its boundary pass wrote,
+        // into frep; its moments go to the replay's own side slots
+        Ctx c = ctx(d);
+        c.side_mom = d->side_mom_rep;
+        launch_main_f32(c, d->f[d->cur ^ 1], d->frep, false);
+        // the ghosts of step t, and the force on the walls during it
+        BndArgs b = bnd_args(d);
+        b.side_mom = d->side_mom_rep;
+        b.do_reduce = 0;
+        b.negrest = nullptr;
+        launch_boundary_f32(c, d->frep, b, b.nlink_blocks + 1);
+        d->force_valid = true;
+        d->replay_valid = true;
+    }
+    return d->frep;
+}
 
 // ------------------------------------------------------------------ arena
 Arena::~Arena() {
@@ -890,7 +982,7 @@ int lbm_moments_device(lbm_domain* d, double* rho, double* ux, double* uy) {
         int rc = dev_alloc(d, (void**)&d->mom_out, 3 * nn * 8);
         if (rc) return rc;
     }
-    launch_main(d, d->f[d->cur ^ 1], nullptr, true);
+    launch_main(d, moments_source(d), nullptr, true);
     if (rho && hipMemcpyAsync(rho, d->mom_out, nn * 8, hipMemcpyDeviceToDevice, d->stream))
         return LBM_EDEVICE;
     if (ux && hipMemcpyAsync(ux, d->mom_out + nn, nn * 8, hipMemcpyDeviceToDevice, d->stream))
@@ -907,7 +999,7 @@ int lbm_moments(lbm_domain* d, double* rho, double* ux, double* uy) {
         int rc = dev_alloc(d, (void**)&d->mom_out, 3 * nn * 8);
         if (rc) return rc;
     }
-    launch_main(d, d->f[d->cur ^ 1], nullptr, true);
+    launch_main(d, moments_source(d), nullptr, true);
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     double* outs[3] = {rho, ux, uy};
     for (int k = 0; k < 3; ++k)
@@ -931,6 +1023,7 @@ int lbm_total_mass(lbm_domain* d, double* out) {
 int lbm_wall_force(lbm_domain* d, double out[2]) {
     if (!d || !out) return LBM_EINVAL;
     out[0] = out[1] = 0.0;
+    if (d->last_fused) (void)moments_source(d);  // the replay forms the force
     if (!d->force_valid) return LBM_OK;
     const int n = link_blocks(d);
     std::vector<double> part((size_t)2 * std::max(n, 1), 0.0);
@@ -992,8 +1085,9 @@ int lbm_get_state(lbm_domain* d, void* buf, size_t* bytes) {
     if (*bytes < need) return LBM_EINVAL;
     if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
     char* p = static_cast<char*>(buf);
+    // word 3: the storage form, and whether the last pass made two steps
     const uint64_t hdr[4] = {kStateMagic, (uint64_t)d->t, ((uint64_t)d->nx << 32 | (uint64_t)d->ny),
-                             (uint64_t)d->storage};
+                             (uint64_t)d->storage | ((uint64_t)(d->last_fused ? 1 : 0) << 32)};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     const size_t fb = d->fbytes;
@@ -1020,8 +1114,10 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
     const char* p = static_cast<const char*>(buf);
     uint64_t hdr[4];
     std::memcpy(hdr, p, sizeof(hdr));
+    const bool fused_state = (hdr[3] >> 32) == 1;
     if (hdr[0] != kStateMagic || hdr[2] != ((uint64_t)d->nx << 32 | (uint64_t)d->ny) ||
-        hdr[3] != (uint64_t)d->storage)
+        (hdr[3] & 0xffffffffULL) != (uint64_t)d->storage || (hdr[3] >> 32) > 1 ||
+        (fused_state && !d->fusable))
         return LBM_EINVAL;
     p += sizeof(hdr);
     if (hipStreamSynchronize(d->stream) != hipSuccess) return LBM_EDEVICE;
@@ -1045,6 +1141,8 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
     const long long tclock = (long long)hdr[1];
     if (hipMemcpy(d->clock, &tclock, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     d->t = (long long)hdr[1];
+    d->last_fused = fused_state;
+    d->replay_valid = false;
     d->pending = false;
     d->pending_t = d->t;
     d->force_valid = false;
@@ -1084,6 +1182,30 @@ int lbm_negative_rest(lbm_domain* d, int64_t* count) {
         hipStreamSynchronize(d->stream) != hipSuccess)
         return LBM_EDEVICE;
     *count = (int64_t)n;
+    return LBM_OK;
+}
+
+int lbm_set_steps_per_pass(lbm_domain* d, int32_t steps, int32_t tile_h) {
+    if (!d || (steps != 1 && steps != 2) || tile_h < 0) return LBM_EINVAL;
+    if (steps == 2 && !d->fusable) return LBM_EINVAL;
+    const int th = tile_h ? tile_h : kTileH2;
+    if (steps == 2) {
+        if (th < kMinTileH2) return LBM_EINVAL;
+        const int ng = (d->ny + th - 1) / th;
+        if ((long long)d->nstrips2 * ng > d->partial_cap) return LBM_EINVAL;
+        d->tile_h2 = th;
+        d->nsegs2 = ng;
+        d->nblocks2 = d->nstrips2 * ng;
+    }
+    drop_graphs(d);
+    d->fused = steps;
+    return LBM_OK;
+}
+
+int lbm_get_steps_per_pass(lbm_domain* d, int32_t* steps, int32_t* tile_h) {
+    if (!d) return LBM_EINVAL;
+    if (steps) *steps = d->fused;
+    if (tile_h) *tile_h = d->fused == 2 ? d->tile_h2 : d->tile_h;
     return LBM_OK;
 }
 

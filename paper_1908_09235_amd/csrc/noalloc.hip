@@ -45,8 +45,9 @@ int moments_into(lbm_domain* d, double* sp, double* rho, double* ux, double* uy)
     Ctx c = domain_ctx(d);
     c.mom_out = sp;
     // the pre-collision moments at t are pulled from f*(t - 1)
-    if (d->storage == LBM_STORE_F64) launch_main_f64(c, d->f[d->cur ^ 1], nullptr, true);
-    else launch_main_f32(c, d->f[d->cur ^ 1], nullptr, true);
+    const void* src = moments_source(d);
+    if (d->storage == LBM_STORE_F64) launch_main_f64(c, src, nullptr, true);
+    else launch_main_f32(c, src, nullptr, true);
     double* outs[3] = {rho, ux, uy};
     for (int k = 0; k < 3; ++k)
         if (outs[k] && hipMemcpyAsync(outs[k], sp + k * nn, nn * sizeof(double),

@@ -86,6 +86,8 @@ EXPORTS = {
     "lbm_kernel_times": (C.c_int, [_H, _D, C.POINTER(C.c_int64), _D,
                                    C.POINTER(C.c_int64)]),
     "lbm_info": (C.c_int, [_H, C.POINTER(C.c_int64)]),
+    "lbm_set_steps_per_pass": (C.c_int, [_H, C.c_int32, C.c_int32]),
+    "lbm_get_steps_per_pass": (C.c_int, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lbm_negative_rest": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_destroy": (None, [_H]),
     "lbm_status_string": (C.c_char_p, [C.c_int]),
@@ -305,6 +307,16 @@ def lbm_wall_force(h):
     out = np.zeros(2)
     _check(lib().lbm_wall_force(h, out.ctypes.data_as(_D)), "lbm_wall_force")
     return out
+
+
+def lbm_set_steps_per_pass(h, steps, tile_h=0):
+    _check(lib().lbm_set_steps_per_pass(h, int(steps), int(tile_h)), "lbm_set_steps_per_pass")
+
+
+def lbm_get_steps_per_pass(h):
+    s, t = C.c_int32(), C.c_int32()
+    _check(lib().lbm_get_steps_per_pass(h, C.byref(s), C.byref(t)), "lbm_get_steps_per_pass")
+    return s.value, t.value
 
 
 def lbm_status_string(code):
