@@ -141,18 +141,18 @@ __device__ __forceinline__ void node_moments(const R fc[9], const R ps[9], const
     Fy = R(0);
     if constexpr (EOS != EOS_NONE) {
         const R w1 = R(wf(1)), w5 = R(wf(5));
-        const R sx = w1 * (ps[1] - ps[3]) + w5 * ((ps[5] - ps[7]) + (ps[8] - ps[6]));
-        const R sy = w1 * (ps[2] - ps[4]) + w5 * ((ps[5] - ps[7]) + (ps[6] - ps[8]));
+        const R sx = fma(w1, ps[1] - ps[3], w5 * ((ps[5] - ps[7]) + (ps[8] - ps[6])));
+        const R sy = fma(w1, ps[2] - ps[4], w5 * ((ps[5] - ps[7]) + (ps[6] - ps[8])));
         const R g = -ph.G * ps[0];
         Fx = g * sx;
         Fy = g * sy;
     }
-    Fx += rho * ph.gx;
-    Fy += rho * ph.gy;
+    Fx = fma(rho, ph.gx, Fx);
+    Fy = fma(rho, ph.gy, Fy);
     const R mx = (fc[1] - fc[3]) + ((fc[5] - fc[7]) + (fc[8] - fc[6]));
     const R my = (fc[2] - fc[4]) + ((fc[5] - fc[7]) + (fc[6] - fc[8]));
-    ux = (mx + R(0.5) * Fx) * irho;
-    uy = (my + R(0.5) * Fy) * irho;
+    ux = fma(R(0.5), Fx, mx) * irho;
+    uy = fma(R(0.5), Fy, my) * irho;
 }
 
 // Columns a strip updates: a workgroup of tile_w lanes also pulls the

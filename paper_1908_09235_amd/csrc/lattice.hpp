@@ -51,6 +51,7 @@ struct Phys {
     R p2G;             // 2 / G
     R rref;            // reference density of deviation storage (else 0)
     R s[9];        // relaxation rates of the nine moments (BGK: all 1/tau)
+    R h[9];        // 1 - s/2: the weight of the forcing source per moment
 };
 
 template <typename R>
@@ -66,14 +67,26 @@ __host__ __device__ __forceinline__ Phys<R> phys_as(const Phys<double>& d) {
     p.p2G = R(d.p2G);
     p.rref = R(d.rref);
     for (int i = 0; i < 9; ++i) p.s[i] = R(d.s[i]);
+    for (int i = 0; i < 9; ++i) p.h[i] = R(d.h[i]);
     return p;
 }
 
 enum { EOS_NONE = 0, EOS_EXP = 1, EOS_CS = 2 };
 
-// Reciprocal and square root: correctly rounded in FP64; the hardware
-// instructions (1 ulp) in FP32.
-__host__ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// Reciprocal and square root.  FP64 reciprocal: the hardware estimate
+// refined by two Newton steps r <- r + r (1 - x r), within an ulp (the
+// argument is a density or a positive power of one); FP64 square root
+// correctly rounded; FP32: the hardware instructions (1 ulp).  On the host,
+// plain division and square root.
+__host__ __device__ __forceinline__ double rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
 __host__ __device__ __forceinline__ double root(double x) { return sqrt(x); }
 __host__ __device__ __forceinline__ float rcp(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -99,11 +112,11 @@ __host__ __device__ __forceinline__ R psi_of(R rho, const Phys<R>& p) {
     } else if constexpr (EOS == EOS_CS) {
         const R a = p.e0, b = p.e1, Rg = p.e2, T = p.e3;
         const R eta = R(0.25) * b * rho;
-        const R num = R(1) + eta * (R(1) + eta * (R(1) - eta));
+        const R num = fma(eta, fma(eta, R(1) - eta, R(1)), R(1));
         const R om = R(1) - eta;
         const R den = om * om * om;
-        const R pe = (rho * Rg * T) * num * rcp(den) - a * rho * rho;
-        return root(p.p2G * (pe - rho * R(1.0 / 3.0)));
+        const R pe = fma(-a * rho, rho, (rho * Rg * T) * num * rcp(den));
+        return root(p.p2G * fma(rho, R(-1.0 / 3.0), pe));
     } else {
         return R(0);
     }
@@ -134,30 +147,28 @@ __device__ __forceinline__ void collide(const R f[9], R rho, R drho, R ux, R uy,
     const R s1 = f[1] + f[3], s2 = f[2] + f[4], c1 = f[5] + f[7], c2 = f[6] + f[8];
     const R d1 = f[1] - f[3], d2 = f[2] - f[4], e1 = f[5] - f[7], e2 = f[6] - f[8];
     const R sa = s1 + s2, sd = c1 + c2;
-    const R m_e = (sd + sd) - sa - R(4) * f[0];
-    const R m_p = R(4) * f[0] - (sa + sa) + sd;
+    const R m_e = fma(R(-4), f[0], (sd + sd) - sa);
+    const R m_p = fma(R(4), f[0], sd - (sa + sa));
     const R m_qx = (e1 - e2) - (d1 + d1);
     const R m_qy = (e1 + e2) - (d2 + d2);
     const R m_xx = s1 - s2, m_xy = c1 - c2;
     const R uxx = ux * ux, uyy = uy * uy, usq = uxx + uyy;
-    const R uF = ux * Fx + uy * Fy;
+    const R uF6 = R(6) * fma(ux, Fx, uy * Fy);
     const R ru2 = R(3) * rho * usq;
-    const R De = p.s[1] * ((ru2 - (drho + drho)) - m_e) + (R(1) - R(0.5) * p.s[1]) * (R(6) * uF);
-    const R Dp = p.s[2] * ((drho - ru2) - m_p) - (R(1) - R(0.5) * p.s[2]) * (R(6) * uF);
-    const R Dqx = -p.s[4] * (rho * ux + m_qx) - (R(1) - R(0.5) * p.s[4]) * Fx;
-    const R Dqy = -p.s[6] * (rho * uy + m_qy) - (R(1) - R(0.5) * p.s[6]) * Fy;
-    const R Dxx = p.s[7] * (rho * (uxx - uyy) - m_xx) +
-                  (R(1) - R(0.5) * p.s[7]) * (R(2) * (ux * Fx - uy * Fy));
-    const R Dxy = p.s[8] * (rho * (ux * uy) - m_xy) +
-                  (R(1) - R(0.5) * p.s[8]) * (ux * Fy + uy * Fx);
+    // h = 1 - s/2 weighs the source moments; multiply-adds written out
+    const R De = fma(p.s[1], (ru2 - (drho + drho)) - m_e, p.h[1] * uF6);
+    const R Dp = fma(p.s[2], (drho - ru2) - m_p, -p.h[2] * uF6);
+    const R Dqx = fma(-p.s[4], fma(rho, ux, m_qx), -p.h[4] * Fx);
+    const R Dqy = fma(-p.s[6], fma(rho, uy, m_qy), -p.h[6] * Fy);
+    const R Dxx = fma(p.s[7], fma(rho, uxx - uyy, -m_xx), p.h[7] * (R(2) * fma(ux, Fx, -uy * Fy)));
+    const R Dxy = fma(p.s[8], fma(rho, ux * uy, -m_xy), p.h[8] * fma(ux, Fy, uy * Fx));
     // M^-1 = M^T diag(1/|row|^2), |row|^2 = 9, 36, 36, 6, 12, 6, 12, 4, 4
-    const R ke = De * R(1.0 / 36.0), kp = Dp * R(1.0 / 36.0);
     const R kjx = Fx * R(1.0 / 6.0), kjy = Fy * R(1.0 / 6.0);
-    const R kqx = Dqx * R(1.0 / 12.0), kqy = Dqy * R(1.0 / 12.0);
     const R kxx = Dxx * R(0.25), kxy = Dxy * R(0.25);
-    const R A = -ke - (kp + kp), B = (ke + ke) + kp;
-    const R X = kjx - (kqx + kqx), Y = kjy - (kqy + kqy);
-    const R P = kjx + kqx, Q = kjy + kqy;
+    const R A = fma(Dp, R(-2.0 / 36.0), De * R(-1.0 / 36.0));
+    const R B = fma(De, R(2.0 / 36.0), Dp * R(1.0 / 36.0));
+    const R X = fma(Dqx, R(-2.0 / 12.0), kjx), Y = fma(Dqy, R(-2.0 / 12.0), kjy);
+    const R P = fma(Dqx, R(1.0 / 12.0), kjx), Q = fma(Dqy, R(1.0 / 12.0), kjy);
     const R g1 = (A + kxx) + X, g3 = (A + kxx) - X;
     const R g2 = (A - kxx) + Y, g4 = (A - kxx) - Y;
     const R bp = B + kxy, bm = B - kxy;

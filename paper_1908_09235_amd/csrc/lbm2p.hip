@@ -117,8 +117,11 @@ Phys<R> make_phys(const lbm_desc* s) {
     p.e3 = R(s->eos_param[3]);
     p.p2G = R(s->G != 0.0 ? 2.0 / s->G : 0.0);
     // BGK is the moment-space collision with every rate 1/tau
-    for (int i = 0; i < 9; ++i)
-        p.s[i] = R(s->collision == LBM_COLL_MRT ? s->mrt_s[i] : 1.0 / s->tau);
+    for (int i = 0; i < 9; ++i) {
+        const double si = s->collision == LBM_COLL_MRT ? s->mrt_s[i] : 1.0 / s->tau;
+        p.s[i] = R(si);
+        p.h[i] = R(1.0 - 0.5 * si);
+    }
     return p;
 }
 
