@@ -36,6 +36,11 @@ ARITH = {"f64": "f64", "f32": "f64", "f32_arith32": "f32", "f32dev": "f32", "f16
          "f16node": "f32"}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1908_09235_amd", "csrc")
@@ -148,6 +153,7 @@ def precision_leg(steps, warmup, stream, prof_steps, check_every, time_steps):
     done = 0
     while done < steps:
         k = min(check_every, steps - done)
+        progress(f"  precision forms at step {done}")
         for st in forms:
             try:
                 doms[st].step(k)
@@ -349,7 +355,9 @@ def batch_leg(steps, n_inst, stream, tune_steps, alone_steps, gate=1e-5):
     probs = [cfg.batch_instance(k) for k in range(n_inst)]
     fluid = np.array([p.fluid_nodes for p in probs], dtype=np.float64)
     b32, s32, st32, r32 = _batch_run(probs, "f32", steps, stream, tune_steps)
+    progress("  FP32 batch done")
     b64, s64, st64, r64 = _batch_run(probs, "f64", steps, stream, tune_steps)
+    progress("  FP64 batch done; comparing every stable instance")
     errs = []
     for k in range(n_inst):
         if st32[k][2] >= 0 or st64[k][2] >= 0:
@@ -422,8 +430,12 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
         i = 0
         t0 = time.perf_counter()
         lu = 0.0
+        last_note = 0.0
         while True:
             now = time.perf_counter() - t0
+            if now - last_note > 20.0:
+                progress(f"  served {len(done_t)} of {len(reqs)} requests, {now:.0f} s")
+                last_note = now
             while i < len(reqs) and reqs[i][0] <= now:
                 _, key, steps = reqs[i]
                 rid = srv.submit(probs[key], steps, history_capacity=1 << 15)
@@ -603,8 +615,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5000,
                     help="steps of each instance of the batched mix (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=512)
-    ap.add_argument("--serve-requests", type=int, default=1000,
-                    help="requests of each served run at a fixed arrival rate (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=500,
+                    help="requests of each served run at a fixed arrival rate (0: skip; "
+                         "1000 puts the 99th percentile at the tenth-longest)")
     ap.add_argument("--serve-check", type=int, default=6,
                     help="served requests compared with an FP64 run of their own")
     ap.add_argument("--serve-chunk", type=int, default=100)
@@ -632,6 +645,7 @@ def main():
     cpu = None
     if a.cpu_seconds > 0:
         procs = a.cpu_procs or min(len(os.sched_getaffinity(0)), 16)
+        progress(f"CPU oracle leg ({procs} copies)")
         cpu = cpu_leg(a.scale, a.cpu_seconds, procs)
 
     import torch
@@ -653,6 +667,7 @@ def main():
         torch.cuda.synchronize()
 
     copy_gbs = copy_bandwidth(torch)
+    progress(f"headline: {workload}, {a.storage}, {a.steps} steps")
     r = run_gpu(p, a.storage, a.steps, a.warmup, stream, a.tile_w, a.tile_h, a.prof_steps)
     fluid = r["info"]["fluid_nodes"]
     s = BYTES_PER_POP[a.storage]
@@ -679,17 +694,22 @@ def main():
 
     prec = None
     if a.precision_steps > 0:
+        progress("precision forms, 8192 x 4096")
         prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_steps,
                              a.precision_check, a.precision_time_steps)
 
     batch = None
     if a.batch_steps > 0:
+        progress(f"batched mix, {a.batch_instances} instances")
         batch = batch_leg(a.batch_steps, a.batch_instances, stream, 3, 500)
     serve = None
     if a.serve_requests > 0:
+        progress(f"served form, {a.serve_requests} requests per rate")
         serve = serve_leg("f32", a.serve_requests, [0.5, 0.8], a.serve_chunk, 128,
                           a.serve_check)
 
+    if a.workloads:
+        progress("the paper's other experiments")
     other = workloads_leg(stream) if a.workloads else None
 
 

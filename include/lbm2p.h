@@ -259,6 +259,15 @@ int lbm_negative_rest(lbm_domain *d, int64_t *count);
 int lbm_set_steps_per_pass(lbm_domain *d, int32_t steps, int32_t tile_h);
 int lbm_get_steps_per_pass(lbm_domain *d, int32_t *steps, int32_t *tile_h);
 
+/* Scheme B (Eq. 22) and Bao et al. (Eq. 23) divide by a sum over the
+ * node's links that can cancel when tau >= 2 (chi < 0 for q < 1/2); where
+ * it vanishes or falls below 1e-12 of the sum of its terms' magnitudes the
+ * node keeps rho_b for that step (a node whose every chi is 0 has no leak
+ * and is not counted).  *count receives the number of such (boundary
+ * node, step) pairs since creation or the last lbm_set_state.  Waits for
+ * the domain's stream. */
+int lbm_degenerate_b(lbm_domain *d, int64_t *count);
+
 /* Facts about the built domain: [0] fluid nodes, [1] cut links,
  * [2] boundary nodes, [3] bytes of device memory held, [4] tile_w,
  * [5] tile_h, [6] main-kernel workgroups, [7] boundary-rule fallbacks
@@ -291,7 +300,10 @@ typedef struct {
                                queues; 0: one workgroup per tile           */
     int32_t graph_steps;    /* steps per captured graph (0 = 32; < 0: no
                                graph, plain launches)                      */
-    int32_t reserved;       /* must be 0                                    */
+    int32_t ring;           /* rows of population loads per lane of the
+                               main pass, the row computed and those in
+                               flight: 2, 3 or 4 (0 = 3; the FP16 per-node
+                               form accepts 0 or 3 only)                   */
     int64_t arena_bytes;    /* device memory for all instances (> 0)        */
     void *stream;           /* compute stream (NULL: the batch makes one)   */
 } lbm_batch_desc;
@@ -326,12 +338,16 @@ int lbm_batch_mass_history(lbm_batch *b, int32_t slot, double *out, int64_t cap,
 int lbm_batch_remove(lbm_batch *b, int32_t slot);
 
 /* Autotuner: runs steps_per_trial real steps of the batch (after one
- * warm-up step) under each main-pass shape (tile_w 64/128/256, tile_h
- * 8/16/32, persistent or not), keeps the fastest and reports it in out:
- * tile_w, tile_h, persistent, microseconds per step.  The steps count as
- * steps of the instances; results do not depend on the shape.  A batch
- * with no instances keeps its shape and reports 0 microseconds. */
-int lbm_batch_tune(lbm_batch *b, int64_t steps_per_trial, int32_t out[4]);
+ * warm-up step) under each main-pass configuration -- columns per
+ * workgroup (tile_w 64/128/256), rows per lane (tile_h 8/16/32),
+ * persistent or not, and rows of population loads each lane keeps in
+ * flight ahead of the row it computes (1, 2 or 3: a ring of 2, 3 or 4
+ * rows of nine populations; the FP16 per-node form always 2) -- keeps the
+ * fastest and reports it in out: tile_w, tile_h, persistent, microseconds
+ * per step, ring rows.  The steps count as steps of the instances; results
+ * do not depend on the configuration.  A batch with no instances keeps its
+ * configuration and reports 0 microseconds. */
+int lbm_batch_tune(lbm_batch *b, int64_t steps_per_trial, int32_t out[5]);
 
 /* [0] instances, [1] main-pass tiles, [2] link blocks, [3] arena bytes,
  * [4] arena bytes in use, [5] tile_w, [6] tile_h, [7] persistent. */

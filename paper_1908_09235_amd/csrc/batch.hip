@@ -49,6 +49,7 @@ struct lbm_batch {
     bool own_stream = false;
     int ncu = 0;
     int tile_w = 256, tile_h = 16, persistent = 1;
+    int ring = 3;  // rows of loads per lane of the main pass (2, 3, 4)
     int graph_steps = 32;
 
     std::vector<lbm_domain*> inst;        // per slot (nullptr: free)
@@ -75,8 +76,9 @@ struct lbm_batch {
     int* h_small = nullptr;  // qbound[9], nlblk
 
     hipGraphExec_t graph = nullptr;
-    // tile_w, persistent, main grid, steps, save_f, boundary grid, reduce grid
-    int graph_key[7] = {0, 0, 0, 0, 0, 0, 0};
+    // tile_w, persistent, main grid, steps, save_f, boundary grid, reduce
+    // grid, ring
+    int graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -267,13 +269,16 @@ BatchLaunch launch_of(lbm_batch* b) {
     L.eos = b->bd.eos;
     L.storage = b->bd.storage;
     L.tile_w = b->tile_w;
+    L.ring = b->bd.storage == LBM_STORE_F16NODE ? 3 : b->ring;
     L.save_f = false;
     for (lbm_domain* d : b->inst)
         if (d && d->save_f) L.save_f = true;
     if (b->persistent) {
         const int occ = b->bd.storage == LBM_STORE_F64
-                            ? batch_occupancy_f64(b->bd.eos, b->bd.storage, b->tile_w, L.save_f)
-                            : batch_occupancy_f32(b->bd.eos, b->bd.storage, b->tile_w, L.save_f);
+                            ? batch_occupancy_f64(b->bd.eos, b->bd.storage, b->tile_w, L.save_f,
+                                                  b->ring)
+                            : batch_occupancy_f32(b->bd.eos, b->bd.storage, b->tile_w, L.save_f,
+                                                  b->ring);
         // no more workgroups than tiles: a small batch would otherwise pay
         // for queue tickets of workgroups that find nothing to do
         L.main_grid = (int)std::min<long long>((long long)b->ncu * std::max(occ, 1),
@@ -305,8 +310,8 @@ int enqueue(lbm_batch* b, long long n) {
     const int G = b->graph_steps;
     long long done = 0;
     if (G > 0 && n >= G) {
-        const int key[7] = {b->tile_w, b->persistent, L.main_grid, G, L.save_f ? 1 : 0,
-                            L.bnd_grid, L.red_grid};
+        const int key[8] = {b->tile_w, b->persistent, L.main_grid, G, L.save_f ? 1 : 0,
+                            L.bnd_grid, L.red_grid, L.ring};
         if (b->graph && std::memcmp(key, b->graph_key, sizeof key) != 0) drop_graph(b);
         if (!b->graph) {
             hipGraph_t g = nullptr;
@@ -412,7 +417,9 @@ int lbm_batch_create(const lbm_batch_desc* bd, lbm_batch** out) {
     if (bd->tile_w != 0 && bd->tile_w != 64 && bd->tile_w != 128 && bd->tile_w != 256)
         return LBM_EINVAL;
     if (bd->tile_h < 0 || (bd->tile_h > 0 && bd->tile_h < 8)) return LBM_EINVAL;
-    if (bd->persistent < 0 || bd->persistent > 1 || bd->reserved != 0) return LBM_EINVAL;
+    if (bd->persistent < 0 || bd->persistent > 1) return LBM_EINVAL;
+    if (bd->ring != 0 && (bd->ring < 2 || bd->ring > 4)) return LBM_EINVAL;
+    if (bd->storage == LBM_STORE_F16NODE && bd->ring != 0 && bd->ring != 3) return LBM_EINVAL;
     if (bd->arena_bytes <= 0) return LBM_EINVAL;
     lbm_batch* b = new (std::nothrow) lbm_batch();
     if (!b) return LBM_ENOMEM;
@@ -420,6 +427,7 @@ int lbm_batch_create(const lbm_batch_desc* bd, lbm_batch** out) {
     b->tile_w = bd->tile_w ? bd->tile_w : 256;
     b->tile_h = bd->tile_h ? bd->tile_h : 16;
     b->persistent = bd->persistent;
+    b->ring = bd->ring ? bd->ring : 3;
     b->graph_steps = bd->graph_steps == 0 ? 32 : std::max(bd->graph_steps, 0);
     int dev = 0;
     hipDeviceProp_t prop;
@@ -529,7 +537,7 @@ int lbm_batch_remove(lbm_batch* b, int32_t slot) {
     return batch_remove(b, slot);
 }
 
-int lbm_batch_tune(lbm_batch* b, int64_t steps_per_trial, int32_t out[4]) {
+int lbm_batch_tune(lbm_batch* b, int64_t steps_per_trial, int32_t out[5]) {
     if (!b || steps_per_trial < 1 || !out) return LBM_EINVAL;
     int rc = sync_batch(b);
     if (rc) return rc;
@@ -540,19 +548,24 @@ int lbm_batch_tune(lbm_batch* b, int64_t steps_per_trial, int32_t out[4]) {
         out[1] = b->tile_h;
         out[2] = b->persistent;
         out[3] = 0;
+        out[4] = b->ring;
         return LBM_OK;
     }
-    const int tws[3] = {64, 128, 256}, ths[3] = {8, 16, 32};
+    const int tws[3] = {64, 128, 256}, ths[3] = {8, 16, 32}, rings[3] = {2, 3, 4};
+    const int nring = b->bd.storage == LBM_STORE_F16NODE ? 1 : 3;
     float best = -1.0f;
-    int bw = b->tile_w, bh = b->tile_h, bp = b->persistent;
+    int bw = b->tile_w, bh = b->tile_h, bp = b->persistent, br = b->ring;
     const int G = b->graph_steps;
     b->graph_steps = 0;  // time plain launches (no capture per candidate)
-    for (int p = 0; p <= 1; ++p)
-        for (int tw : tws)
-            for (int th : ths) {
+    for (int ri = 0; ri < nring && !rc; ++ri)
+        for (int p = 0; p <= 1 && !rc; ++p)
+            for (int wi = 0; wi < 3 && !rc; ++wi)
+                for (int hi = 0; hi < 3 && !rc; ++hi) {
+                const int tw = tws[wi], th = ths[hi];
                 b->tile_w = tw;
                 b->tile_h = th;
                 b->persistent = p;
+                b->ring = nring == 1 ? 3 : rings[ri];
                 b->dirty = true;
                 if ((rc = enqueue(b, 1))) break;  // rebuild, warm up
                 if (hipEventRecord(b->ev0, b->stream) != hipSuccess) rc = LBM_EDEVICE;
@@ -570,18 +583,21 @@ int lbm_batch_tune(lbm_batch* b, int64_t steps_per_trial, int32_t out[4]) {
                     bw = tw;
                     bh = th;
                     bp = p;
+                    br = b->ring;
                 }
             }
     b->graph_steps = G;
     b->tile_w = bw;
     b->tile_h = bh;
     b->persistent = bp;
+    b->ring = br;
     b->dirty = true;
     if (rc) return rc;
     out[0] = bw;
     out[1] = bh;
     out[2] = bp;
     out[3] = (int32_t)(best * 1000.0f / (float)steps_per_trial);  // us per step
+    out[4] = br;
     return LBM_OK;
 }
 

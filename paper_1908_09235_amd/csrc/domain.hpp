@@ -62,6 +62,7 @@ struct lbm_domain {
     double inlet_u = 0.0;
     double* force = nullptr;   // wall force partials, two per link block
     unsigned long long* negrest = nullptr;  // scheme A: negative rest count
+    unsigned long long* degen = nullptr;    // scheme B / Bao: cancelled sums count
     bool force_valid = false;  // a boundary pass has written them
     int nb = 0, nl = 0;
     int nslot_links = 0;

@@ -46,6 +46,7 @@ struct Main2Args {
     const double* __restrict__ lc;
     const double* __restrict__ luw;
     unsigned long long* __restrict__ negrest;
+    unsigned long long* __restrict__ degen;
     int fix;
     int nx, ny, pitch;
     long long plane;
@@ -237,6 +238,7 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
                 }
             }
             if (den != 0.0 && fabs(den) > 1e-12 * mag) rho_s = num / den;
+            else if (bnd && own && mag > 0.0 && a.degen) atomicAdd(a.degen, 1ull);
         }
         for (int l = 0; l < len; ++l) {
             double fab, ch, bk, wl;

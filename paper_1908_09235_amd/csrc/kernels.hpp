@@ -177,9 +177,12 @@ __host__ __device__ constexpr int strip_cols(int tile_w) { return tile_w - 2; }
 // returns 0).  Solid nodes keep psi of their wall density in their own
 // rest slot (plane 0), which nothing else reads or writes; with FP16
 // storage it is read in FP32 from a per-node array instead.
-template <typename S, typename R, int EOS, bool MOMENTS, int DEV, bool SAVEF>
+template <typename S, typename R, int EOS, bool MOMENTS, int DEV, bool SAVEF, int RING = 3>
 __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& ph,
                                           int tile) {
+    // RING rows of loads: RING - 1 rows are in flight while a row is
+    // computed (the FP16 per-node form's density ring assumes three)
+    static_assert(RING >= 2 && RING <= 4 && (DEV != 2 || RING == 3), "unsupported ring");
     __shared__ R ring[4][kMaxTileW];
     __shared__ double wsum[kMaxTileW / 64];
     constexpr unsigned ES = sizeof(S);
@@ -406,10 +409,10 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
             if constexpr (DEV == 2)
                 bstore(float(rho), rd, live ? x * 4u : kOOB, rbase + (unsigned)y * pitch * 4u);
         }
-        issue(k + 3, Lc);  // Lc is free again
+        issue(k + RING, Lc);  // Lc is free again
     };
 
-    RowLoad<S, R, NR> A, B, C;
+    RowLoad<S, R, NR> L[RING];
     // DEV 2: density rows -2 .. 0 here, 1 and 2 with the first two issues
     RowLoad<S, R, NR> D0, D1, D2;
     if constexpr (DEV == 2) {
@@ -418,26 +421,25 @@ __device__ __forceinline__ void main_tile(const MainArgs<S>& a, const Phys<R>& p
         load_dens(0, D2);
     }
     load_flags(-1);
-    issue(-1, C);
-    issue(0, A);
-    issue(1, B);
+    issue(-1, L[RING - 1]);
+#pragma unroll
+    for (int i = 0; i + 1 < RING; ++i) issue(i, L[i]);
     if constexpr (DEV == 2) {
         put_dens(-2, D0);
         put_dens(-1, D1);
         put_dens(0, D2);
-        put_dens(1, C);
-        put_dens(2, A);
+        put_dens(1, L[2]);
+        put_dens(2, L[0]);
         __syncthreads();
     }
-    publish(C, -1);
-    issue(2, C);
-    publish(A, 0);
-    // a whole number of three-row rotations; rows k >= H store nothing
-    const int H3 = (H + 2) / 3 * 3;
-    for (int k = 0; k < H3; k += 3) {
-        step(k, A, B);
-        step(k + 1, B, C);
-        step(k + 2, C, A);
+    publish(L[RING - 1], -1);
+    issue(RING - 1, L[RING - 1]);
+    publish(L[0], 0);
+    // a whole number of ring rotations; rows k >= H store nothing
+    const int HR = (H + RING - 1) / RING * RING;
+    for (int k = 0; k < HR; k += RING) {
+#pragma unroll
+        for (int i = 0; i < RING; ++i) step(k + i, L[i], L[(i + 1) % RING]);
     }
 
     if constexpr (!MOMENTS) {
@@ -593,6 +595,9 @@ struct BndArgs {
     // scheme A: count of boundary nodes whose rest population came out
     // negative (null: not counted)
     unsigned long long* __restrict__ negrest;
+    // scheme B / Bao: count of boundary nodes whose sums in Eq. (22) or
+    // (23) cancel, which keep rho_b (null: not counted)
+    unsigned long long* __restrict__ degen;
 };
 
 constexpr int LK_PAD = 15;
@@ -720,7 +725,10 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
                     mag += fabs(s_br[tid + m]);
                 }
             }
-            s_rhos[tid] = (den != 0.0 && fabs(den) > 1e-12 * mag) ? num / den : NAN;
+            const bool ok = den != 0.0 && fabs(den) > 1e-12 * mag;
+            s_rhos[tid] = ok ? num / den : NAN;
+            // (a node whose every chi is 0 has no leak and is not counted)
+            if (!ok && mag > 0.0 && b.degen) atomicAdd(b.degen, 1ull);
         }
         __syncthreads();
         if (active) {
@@ -967,15 +975,15 @@ __device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long 
     return a;
 }
 
-template <typename S, typename R, int EOS, int DEV, bool SAVEF>
+template <typename S, typename R, int EOS, int DEV, bool SAVEF, int RING>
 __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
     g = __builtin_amdgcn_readfirstlane(g);
     const int2 te = b.tiles[g];
     const BState st = b.state[te.x];
     if (st.remaining <= 0) return;
     const BInst& I = b.inst[te.x];
-    main_tile<S, R, EOS, false, DEV, SAVEF>(inst_main_args<S>(I, st.t, b.tile_h), phys_as<R>(I.ph),
-                                     te.y);
+    main_tile<S, R, EOS, false, DEV, SAVEF, RING>(inst_main_args<S>(I, st.t, b.tile_h),
+                                                  phys_as<R>(I.ph), te.y);
 }
 
 // Persistent form: a fixed grid; each workgroup takes tiles from the queue
@@ -983,14 +991,14 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
 // the other queues in turn, until all are empty.  The queues hold
 // contiguous runs of the tile list, so one XCD works through compact
 // pieces of the same instances and finds their halos in its L2.
-template <typename S, typename R, int EOS, int DEV, bool SAVEF>
+template <typename S, typename R, int EOS, int DEV, bool SAVEF, int RING>
 // (three wavefronts per SIMD: the instance arguments add registers to the
 // tile's, and the benchmark's form would otherwise need one more than three
 // wavefronts leave)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_main_batch(
     BatchArgs b) {
     if (!b.persistent) {
-        batch_tile<S, R, EOS, DEV, SAVEF>(b, xcd_tile(blockIdx.x, gridDim.x));
+        batch_tile<S, R, EOS, DEV, SAVEF, RING>(b, xcd_tile(blockIdx.x, gridDim.x));
         return;
     }
     __shared__ int s_g;
@@ -1014,7 +1022,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         __syncthreads();
         const int g = s_g;
         if (g < 0) break;
-        batch_tile<S, R, EOS, DEV, SAVEF>(b, g);
+        batch_tile<S, R, EOS, DEV, SAVEF, RING>(b, g);
     }
 }
 
@@ -1053,6 +1061,7 @@ __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
         a.do_reduce = 0;
         a.force = nullptr;
         a.negrest = nullptr;
+        a.degen = nullptr;
         a.nlink_blocks = 0;
         a.open_x = 0;
         a.nx = a.ny = a.pitch = 0;

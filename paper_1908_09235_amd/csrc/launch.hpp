@@ -35,6 +35,7 @@ struct Ctx {
     const double* lc;
     const double* luw;
     unsigned long long* negrest;
+    unsigned long long* degen;
     int fix;
 };
 
@@ -67,6 +68,7 @@ struct BatchLaunch {
     int main_grid;  // persistent: workgroups; otherwise: tiles
     bool save_f;    // some instance saves pre-collision populations
     int bnd_grid;
+    int ring;       // rows of loads per lane of the main pass (2, 3, 4)
     int red_grid;
     hipStream_t stream;
 };
@@ -74,7 +76,7 @@ void launch_batch_f64(const BatchLaunch& L);
 void launch_batch_f32(const BatchLaunch& L);
 void launch_batch_reduce(const BatchLaunch& L);
 // resident workgroups per CU of the batched main kernel
-int batch_occupancy_f64(int eos, int storage, int tile_w, bool save_f);
-int batch_occupancy_f32(int eos, int storage, int tile_w, bool save_f);
+int batch_occupancy_f64(int eos, int storage, int tile_w, bool save_f, int ring);
+int batch_occupancy_f32(int eos, int storage, int tile_w, bool save_f, int ring);
 
 }  // namespace lbm

@@ -53,13 +53,13 @@ void launch_batch_f32(const BatchLaunch& L) {
     default: batch_any<float, double, 0>(L);
     }
 }
-int batch_occupancy_f32(int eos, int storage, int tile_w, bool save_f) {
+int batch_occupancy_f32(int eos, int storage, int tile_w, bool save_f, int ring) {
     switch (storage) {
-    case 2: return occupancy_any<float, float, 0>(eos, tile_w, save_f);
-    case 3: return occupancy_any<float, float, 1>(eos, tile_w, save_f);
-    case 4: return occupancy_any<_Float16, float, 1>(eos, tile_w, save_f);
-    case 5: return occupancy_any<_Float16, float, 2>(eos, tile_w, save_f);
-    default: return occupancy_any<float, double, 0>(eos, tile_w, save_f);
+    case 2: return occupancy_any<float, float, 0>(eos, tile_w, save_f, ring);
+    case 3: return occupancy_any<float, float, 1>(eos, tile_w, save_f, ring);
+    case 4: return occupancy_any<_Float16, float, 1>(eos, tile_w, save_f, ring);
+    case 5: return occupancy_any<_Float16, float, 2>(eos, tile_w, save_f, ring);
+    default: return occupancy_any<float, double, 0>(eos, tile_w, save_f, ring);
     }
 }
 

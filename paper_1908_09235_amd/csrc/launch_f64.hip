@@ -25,8 +25,8 @@ void launch_batch_f64(const BatchLaunch& L) { batch_any<double, double, 0>(L); }
 void launch_batch_reduce(const BatchLaunch& L) {
     hipLaunchKernelGGL(k_reduce_batch<0>, dim3(L.red_grid), dim3(256), 0, L.stream, L.args);
 }
-int batch_occupancy_f64(int eos, int, int tile_w, bool save_f) {
-    return occupancy_any<double, double, 0>(eos, tile_w, save_f);
+int batch_occupancy_f64(int eos, int, int tile_w, bool save_f, int ring) {
+    return occupancy_any<double, double, 0>(eos, tile_w, save_f, ring);
 }
 
 }  // namespace lbm

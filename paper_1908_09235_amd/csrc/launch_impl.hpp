@@ -67,6 +67,7 @@ void main2_t(const Ctx& c, const S* src, S* dst) {
     a.lc = c.lc;
     a.luw = c.luw;
     a.negrest = c.negrest;
+    a.degen = c.degen;
     a.fix = c.fix;
     a.nx = c.nx;
     a.ny = c.ny;
@@ -115,17 +116,29 @@ void init_any(const Ctx& c, const double* rw, const double* r0, const double* u0
                        c.nx, c.ny, c.pitch, c.plane, c.ph.rref, c.ref);
 }
 
-template <typename S, typename R, int DEV, bool SAVEF>
-void batch_main(const BatchLaunch& L) {
+template <typename S, typename R, int DEV, bool SAVEF, int RING>
+void batch_main_r(const BatchLaunch& L) {
     if (L.eos == EOS_EXP)
-        hipLaunchKernelGGL((k_main_batch<S, R, EOS_EXP, DEV, SAVEF>), dim3(L.main_grid),
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_EXP, DEV, SAVEF, RING>), dim3(L.main_grid),
                            dim3(L.tile_w), 0, L.stream, L.args);
     else if (L.eos == EOS_CS)
-        hipLaunchKernelGGL((k_main_batch<S, R, EOS_CS, DEV, SAVEF>), dim3(L.main_grid),
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_CS, DEV, SAVEF, RING>), dim3(L.main_grid),
                            dim3(L.tile_w), 0, L.stream, L.args);
     else
-        hipLaunchKernelGGL((k_main_batch<S, R, EOS_NONE, DEV, SAVEF>), dim3(L.main_grid),
+        hipLaunchKernelGGL((k_main_batch<S, R, EOS_NONE, DEV, SAVEF, RING>), dim3(L.main_grid),
                            dim3(L.tile_w), 0, L.stream, L.args);
+}
+
+// rows of loads per lane: the ring L.ring (the FP16 per-node form: 3 only)
+template <typename S, typename R, int DEV, bool SAVEF>
+void batch_main(const BatchLaunch& L) {
+    if constexpr (DEV == 2) {
+        batch_main_r<S, R, DEV, SAVEF, 3>(L);
+    } else {
+        if (L.ring == 2) batch_main_r<S, R, DEV, SAVEF, 2>(L);
+        else if (L.ring == 4) batch_main_r<S, R, DEV, SAVEF, 4>(L);
+        else batch_main_r<S, R, DEV, SAVEF, 3>(L);
+    }
 }
 
 template <typename S, typename R, int DEV>
@@ -136,26 +149,37 @@ void batch_any(const BatchLaunch& L) {
     else batch_main<S, R, DEV, false>(L);
 }
 
-template <typename S, typename R, int DEV, bool SAVEF>
+template <typename S, typename R, int DEV, bool SAVEF, int RING>
 int occupancy_e(int eos, int tile_w) {
     int n = 0;
     hipError_t e;
     if (eos == EOS_EXP)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_EXP, DEV, SAVEF>), tile_w, 0);
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_EXP, DEV, SAVEF, RING>),
+            tile_w, 0);
     else if (eos == EOS_CS)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_CS, DEV, SAVEF>), tile_w, 0);
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_CS, DEV, SAVEF, RING>),
+            tile_w, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_NONE, DEV, SAVEF>), tile_w, 0);
+            &n, reinterpret_cast<const void*>(k_main_batch<S, R, EOS_NONE, DEV, SAVEF, RING>),
+            tile_w, 0);
     return e == hipSuccess ? n : 0;
 }
 
 template <typename S, typename R, int DEV>
-int occupancy_any(int eos, int tile_w, bool save_f) {
-    return save_f ? occupancy_e<S, R, DEV, true>(eos, tile_w)
-                  : occupancy_e<S, R, DEV, false>(eos, tile_w);
+int occupancy_any(int eos, int tile_w, bool save_f, int ring) {
+    if constexpr (DEV != 2) {
+        if (ring == 2)
+            return save_f ? occupancy_e<S, R, DEV, true, 2>(eos, tile_w)
+                          : occupancy_e<S, R, DEV, false, 2>(eos, tile_w);
+        if (ring == 4)
+            return save_f ? occupancy_e<S, R, DEV, true, 4>(eos, tile_w)
+                          : occupancy_e<S, R, DEV, false, 4>(eos, tile_w);
+    }
+    return save_f ? occupancy_e<S, R, DEV, true, 3>(eos, tile_w)
+                  : occupancy_e<S, R, DEV, false, 3>(eos, tile_w);
 }
 
 }  // namespace lbm

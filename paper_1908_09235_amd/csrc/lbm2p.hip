@@ -168,6 +168,7 @@ Ctx ctx(lbm_domain* d) {
     c.lc = d->lc;
     c.luw = d->luw;
     c.negrest = d->negrest;
+    c.degen = d->degen;
     c.fix = d->fix;
     return c;
 }
@@ -207,6 +208,7 @@ BndArgs bnd_args(lbm_domain* d) {
     b.clock = d->clock;
     b.force = d->force;
     b.negrest = d->negrest;
+    b.degen = d->degen;
     b.nlink_blocks = link_blocks(d);
     b.open_x = d->open_x;
     b.nx = d->nx;
@@ -780,6 +782,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
 
     if ((rc = dev_alloc(d, (void**)&d->negrest, 8))) return rc;
     if (hipMemsetAsync(d->negrest, 0, 8, d->stream) != hipSuccess) return LBM_EDEVICE;
+    if ((rc = dev_alloc(d, (void**)&d->degen, 8))) return rc;
+    if (hipMemsetAsync(d->degen, 0, 8, d->stream) != hipSuccess) return LBM_EDEVICE;
 
     // no unstable step yet; the first recorded mass is that of step 0
     static const long long minus1 = -1;
@@ -886,6 +890,7 @@ const void* moments_source(lbm_domain* d) {
         b.side_mom = d->side_mom_rep;
         b.do_reduce = 0;
         b.negrest = nullptr;
+        b.degen = nullptr;
         launch_boundary_f32(c, d->frep, b, b.nlink_blocks + 1);
         d->force_valid = true;
         d->replay_valid = true;
@@ -1140,7 +1145,8 @@ int lbm_set_state(lbm_domain* d, const void* buf, size_t bytes) {
         return LBM_EDEVICE;
     p += (size_t)d->cap * 8;
     if (hipMemcpy(d->unstable, p, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
-    if (hipMemset(d->negrest, 0, 8) != hipSuccess) return LBM_EDEVICE;
+    if (hipMemset(d->negrest, 0, 8) != hipSuccess || hipMemset(d->degen, 0, 8) != hipSuccess)
+        return LBM_EDEVICE;
     const long long tclock = (long long)hdr[1];
     if (hipMemcpy(d->clock, &tclock, 8, hipMemcpyHostToDevice) != hipSuccess) return LBM_EDEVICE;
     d->t = (long long)hdr[1];
@@ -1209,6 +1215,16 @@ int lbm_get_steps_per_pass(lbm_domain* d, int32_t* steps, int32_t* tile_h) {
     if (!d) return LBM_EINVAL;
     if (steps) *steps = d->fused;
     if (tile_h) *tile_h = d->fused == 2 ? d->tile_h2 : d->tile_h;
+    return LBM_OK;
+}
+
+int lbm_degenerate_b(lbm_domain* d, int64_t* count) {
+    if (!d || !count) return LBM_EINVAL;
+    unsigned long long n = 0;
+    if (hipMemcpyAsync(&n, d->degen, 8, hipMemcpyDeviceToHost, d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    *count = (int64_t)n;
     return LBM_OK;
 }
 

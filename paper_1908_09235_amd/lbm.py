@@ -57,7 +57,7 @@ class lbm_batch_desc(C.Structure):
     _fields_ = [("storage", C.c_int32), ("eos", C.c_int32),
                 ("max_instances", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("persistent", C.c_int32),
-                ("graph_steps", C.c_int32), ("reserved", C.c_int32),
+                ("graph_steps", C.c_int32), ("ring", C.c_int32),
                 ("arena_bytes", C.c_int64), ("stream", C.c_void_p)]
 
 
@@ -89,6 +89,7 @@ EXPORTS = {
     "lbm_set_steps_per_pass": (C.c_int, [_H, C.c_int32, C.c_int32]),
     "lbm_get_steps_per_pass": (C.c_int, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lbm_negative_rest": (C.c_int, [_H, C.POINTER(C.c_int64)]),
+    "lbm_degenerate_b": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_destroy": (None, [_H]),
     "lbm_status_string": (C.c_char_p, [C.c_int]),
     "lbm_batch_create": (C.c_int, [C.POINTER(lbm_batch_desc), C.POINTER(_H)]),
@@ -290,6 +291,12 @@ def lbm_negative_rest(h):
     return n.value
 
 
+def lbm_degenerate_b(h):
+    n = C.c_int64()
+    _check(lib().lbm_degenerate_b(h, C.byref(n)), "lbm_degenerate_b")
+    return n.value
+
+
 def lbm_info(h):
     out = (C.c_int64 * 8)()
     _check(lib().lbm_info(h, out), "lbm_info")
@@ -355,6 +362,9 @@ class Domain:
     def negative_rest(self):
         return lbm_negative_rest(self.h)
 
+    def degenerate_b(self):
+        return lbm_degenerate_b(self.h)
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             lbm_destroy(self.h)
@@ -375,7 +385,7 @@ class Domain:
 
 # ---------------------------------------------------------------- batches
 def make_batch_desc(storage="f32", eos="cs", max_instances=1024, tile_w=0, tile_h=0,
-                    persistent=1, graph_steps=0, arena_bytes=1 << 30, stream=None):
+                    persistent=1, graph_steps=0, arena_bytes=1 << 30, stream=None, ring=0):
     bd = lbm_batch_desc()
     bd.storage = STORAGE[storage]
     bd.eos = EOS[eos]
@@ -383,7 +393,7 @@ def make_batch_desc(storage="f32", eos="cs", max_instances=1024, tile_w=0, tile_
     bd.tile_w, bd.tile_h = tile_w, tile_h
     bd.persistent = persistent
     bd.graph_steps = graph_steps
-    bd.reserved = 0
+    bd.ring = ring
     bd.arena_bytes = int(arena_bytes)
     bd.stream = stream
     return bd
@@ -439,9 +449,10 @@ def lbm_batch_remove(h, slot):
 
 
 def lbm_batch_tune(h, steps_per_trial):
-    out = (C.c_int32 * 4)()
+    out = (C.c_int32 * 5)()
     _check(lib().lbm_batch_tune(h, int(steps_per_trial), out), "lbm_batch_tune")
-    return {"tile_w": out[0], "tile_h": out[1], "persistent": out[2], "us_per_step": out[3]}
+    return {"tile_w": out[0], "tile_h": out[1], "persistent": out[2], "us_per_step": out[3],
+            "ring": out[4]}
 
 
 def lbm_batch_info(h):

@@ -184,10 +184,12 @@ def test_batch_descriptors_are_validated(L):
                 dict(arena_bytes=0)):
         bd = L.make_batch_desc(**{**good, **bad})
         assert lib.lbm_batch_create(ctypes.byref(bd), ctypes.byref(h)) == L.LBM_EINVAL, bad
-    for field, val in (("storage", 9), ("eos", 3), ("reserved", 1)):
+    for field, val in (("storage", 9), ("eos", 3), ("ring", 1), ("ring", 5)):
         bd = L.make_batch_desc(**good)
         setattr(bd, field, val)
         assert lib.lbm_batch_create(ctypes.byref(bd), ctypes.byref(h)) == L.LBM_EINVAL, field
+    bd = L.make_batch_desc(**{**good, "storage": "f16node", "ring": 2})
+    assert lib.lbm_batch_create(ctypes.byref(bd), ctypes.byref(h)) == L.LBM_EINVAL
     bd = L.make_batch_desc(**good)
     assert lib.lbm_server_create(ctypes.byref(bd), 0, ctypes.byref(h)) == L.LBM_EINVAL
     assert lib.lbm_batch_create(None, ctypes.byref(h)) == L.LBM_EINVAL

@@ -114,13 +114,14 @@ def test_arena_admission_limit(L):
 
 def test_autotuner_keeps_results(L):
     probs = small_mix(5, 64, 300)
-    steps = 3 * 18 * 2 + 40
+    steps = 3 * 54 + 40
     with L.Batch(storage="f64", eos="cs", max_instances=8, arena_bytes=1 << 30) as b:
         slots = [b.add(p, steps, history_capacity=1024) for p in probs]
-        best = b.tune(2)  # 18 shapes x (1 warm-up + 2) steps
+        best = b.tune(2)  # 54 configurations x (1 warm-up + 2) steps
         say(f"    tuned {best}")
         assert best["tile_w"] in (64, 128, 256) and best["tile_h"] in (8, 16, 32)
         assert best["persistent"] in (0, 1) and best["us_per_step"] > 0
+        assert best["ring"] in (2, 3, 4)
         info = b.info()
         assert (info["tile_w"], info["tile_h"]) == (best["tile_w"], best["tile_h"])
         b.run(steps)
@@ -132,6 +133,23 @@ def test_autotuner_keeps_results(L):
             # fields do not depend on the tile shape (the mass history's last
             # bits do: partials are summed per tile)
             a_mom, _, a_u = alone(L, p, n, "f64")
+            assert a_u == u and same(b.moments(s), a_mom)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("ring", [2, 3, 4])
+def test_ring_rows_keep_results(L, storage, ring):
+    """Rows of loads in flight per lane (ring 2, 3, 4): every instance
+    bit-identical to the same problem run alone."""
+    probs = small_mix(3, 64, 200)
+    with L.Batch(storage=storage, eos="cs", max_instances=4, arena_bytes=1 << 29, ring=ring,
+                 tile_w=128, tile_h=16) as b:
+        slots = [b.add(p, 60, history_capacity=128) for p in probs]
+        b.run(60)
+        for s, p in zip(slots, probs):
+            t, _, u = b.status(s)
+            a_mom, _, a_u = alone(L, p, t, storage, 128, 16)
+            say(f"    ring {ring} {storage} {p.name}: t={t} unstable={u}")
             assert a_u == u and same(b.moments(s), a_mom)
 
 

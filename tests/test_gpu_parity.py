@@ -495,3 +495,23 @@ def test_resting_cylinder_array_convergence_on_gpu(L, fix):
     diffs = np.abs(np.diff(ks))
     say(f"    {fix}: |k(2d) - k(d)| {np.array2string(diffs, precision=3)}")
     assert diffs[-1] < diffs[0]
+
+
+@pytest.mark.parametrize("storage,steps_per_pass", [("f64", 1), ("f32", 1), ("f32", 2)])
+def test_scheme_b_cancelling_sums_count(L, storage, steps_per_pass):
+    """The (node, step) pairs where the sums of Eq. (22) cancel, counted by
+    the library as by the oracle (eight nodes per step in the constructed
+    case), also when two steps are made per pass."""
+    from tests.test_oracle_physics import _cancelling_b_case
+    p = _cancelling_b_case()
+    o = ora.Oracle(p)
+    o.step(10)
+    want = int(o.counters()[3])
+    say(f"[gpu] cancelling scheme-B sums, {storage}, {steps_per_pass} steps per pass")
+    with L.Domain(p, storage=storage) as d:
+        L.lbm_set_steps_per_pass(d.h, steps_per_pass)
+        d.step(10)
+        assert d.degenerate_b() == want == 80
+        r, ux, uy = d.moments()
+    fl = ~p.solid.astype(bool)
+    assert np.abs(r[fl] - 1.0).max() < 1e-6 and np.abs(ux[fl]).max() < 1e-12

@@ -448,3 +448,45 @@ def test_resting_cylinder_array_A_B_mass_exact_and_consistent():
         rel = [abs(K[(d, f)] / K[(d, "none")] - 1) for d in ds]
         assert rel[-1] < rel[0], (f, rel)
         assert rel[-1] < 0.015, (f, rel)
+
+
+def _cancelling_b_case(tau=3.0):
+    """An 8 x 8 periodic lattice at rest with solid columns x = 2 and 4:
+    each node of column 3 has three links into column 4 with q = 0.8
+    (chi = 0.6/tau) and three into column 2 with q = 0.4
+    (chi = -0.2/(tau - 2)), so at tau = 3 the sums of Eq. (22) cancel
+    there (the weights pair up: 1/9 + 2/36 on either side)."""
+    from lbm_inputs.problem import LINK_DTYPE, Problem
+    n = 8
+    solid = np.zeros((n, n), np.uint8)
+    solid[:, 2] = 1
+    solid[:, 4] = 1
+    EXd = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    recs = []
+    for y in range(n):
+        for x in range(n):
+            if solid[y, x]:
+                continue
+            for d in range(1, 9):
+                xs, ys = (x + EXd[d]) % n, (y + [0, 0, 1, 0, -1, 1, 1, -1, -1][d]) % n
+                if solid[ys, xs]:
+                    q = 0.8 if xs == 4 and x == 3 else (0.4 if xs == 2 and x == 3 else 0.5)
+                    recs.append((x, y, d, 0, q, 0.0, 0.0))
+    links = np.array(recs, dtype=LINK_DTYPE)
+    return Problem(nx=n, ny=n, solid=solid, links=links, rho0=np.ones((n, n)),
+                   rho_wall=np.ones((n, n)), eos="none", tau=tau, rule="mls", fix="B",
+                   name="cancelling_b")
+
+
+def test_scheme_b_cancelling_sums_are_counted_and_keep_rho_b():
+    """Where the denominator of Eq. (22) cancels the node keeps rho_b and
+    is counted once per step: the eight nodes of column 3 each step; the
+    fluid stays at rest (MLS with rho_b returns f* = w rho for u = 0)."""
+    p = _cancelling_b_case()
+    o = ora.Oracle(p)
+    o.step(10)
+    assert o.counters()[3] == 8 * 10
+    r, ux, uy = o.moments()
+    fl = _fluid(p)
+    assert np.allclose(r[fl], 1.0, rtol=0, atol=1e-15)
+    assert np.abs(ux[fl]).max() < 1e-16 and np.abs(uy[fl]).max() < 1e-16
