@@ -174,7 +174,7 @@ def precision_leg(steps, warmup, stream, prof_steps, check_every, time_steps):
                 if within[st][t] is None and e.max() > t:
                     within[st][t] = done - k  # the last check that held
     out = {"workload": f"{p.name}_bgk_mls_B", "steps": steps, "check_every": check_every,
-           "fluid_nodes": fluid}
+           "fluid_nodes": fluid, "wettability": cfg.REALISED_WETTABILITY}
     for st in forms:
         d = doms[st]
         drift = abs(d.total_mass() - m0[st]) / m0[st]
