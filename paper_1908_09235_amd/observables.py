@@ -58,31 +58,35 @@ def _bilinear(f, x, y):
             (1 - tx) * ty * f[y0 + 1, x0] + tx * ty * f[y0 + 1, x0 + 1])
 
 
-def separation_angle(ux, uy, solid, cx, cy, r, deltas=(1.5, 2.5)):
-    """theta_s in degrees, upper and lower halves averaged."""
+def separation_angle(ux, uy, solid, cx, cy, r, deltas=(1.0, 1.5, 2.0, 2.5, 3.0)):
+    """theta_s in degrees (upper and lower halves averaged): where the wall
+    shear changes sign.  At each angle phi from the rear stagnation point
+    the tangential velocity u_t on circles of radius r + delta (bilinear,
+    solid nodes at rest) is fitted by u_t = a delta + b delta^2, which
+    vanishes at the wall; the separation point is where a(phi) turns
+    negative (reverse flow along the wall), linear between samples."""
     fl = ~solid.astype(bool)
     u = np.where(fl, ux, 0.0)
     v = np.where(fl, uy, 0.0)
-    phi = np.radians(np.linspace(1.0, 120.0, 23801))
+    phi = np.radians(np.linspace(1.0, 120.0, 11901))
+    dl = np.asarray(deltas, dtype=np.float64)
+    basis = np.c_[dl, dl * dl]
     out = []
-    for dl in deltas:
-        rr = r + dl
-        side = []
-        for sgn in (1.0, -1.0):
-            x = cx + rr * np.cos(phi)
-            y = cy + sgn * rr * np.sin(phi)
+    for sgn in (1.0, -1.0):
+        ut = []
+        for d in dl:
+            x = cx + (r + d) * np.cos(phi)
+            y = cy + sgn * (r + d) * np.sin(phi)
             # the lower half is the mirror image: v changes sign
-            ut = -_bilinear(u, x, y) * np.sin(phi) + sgn * _bilinear(v, x, y) * np.cos(phi)
-            # reverse flow (u_t > 0) behind the separation point
-            k = int(np.argmax(ut < 0))
-            if k == 0:
-                side.append(0.0)
-                continue
-            t = ut[k - 1] / (ut[k - 1] - ut[k])
-            side.append(np.degrees(phi[k - 1] + t * (phi[k] - phi[k - 1])))
-        out.append(0.5 * (side[0] + side[1]))
-    (d1, d2), (a1, a2) = deltas, out
-    return a1 + (a1 - a2) * d1 / (d2 - d1)
+            ut.append(-_bilinear(u, x, y) * np.sin(phi) + sgn * _bilinear(v, x, y) * np.cos(phi))
+        a = np.linalg.lstsq(basis, np.array(ut), rcond=None)[0][0]
+        k = int(np.argmax(a < 0))
+        if k == 0:
+            out.append(0.0)
+            continue
+        t = a[k - 1] / (a[k - 1] - a[k])
+        out.append(np.degrees(phi[k - 1] + t * (phi[k] - phi[k - 1])))
+    return 0.5 * (out[0] + out[1])
 
 
 def interface_points(rho, solid, level):
