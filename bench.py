@@ -403,7 +403,8 @@ def batch_leg(steps, n_inst, stream, tune_steps, alone_steps, gate=1e-5):
     return out
 
 
-def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
+def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5,
+              gate_storage="f64"):
     """The served workload: Poisson arrivals of droplet-on-cylinder
     requests (95 % the batched mix, 5 % 2048^2; 2000..20000 steps each) into
     one server.  First a saturated run (every request present at t = 0)
@@ -411,7 +412,9 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
     n_requests arrive at each rate in `rates` (fractions of it) for
     time-to-solution percentiles.  The first n_check stable requests of the
     first rate (and its first 2048^2 one) are run again alone in FP64
-    storage and compared (max-norm relative over fluid nodes)."""
+    storage and compared (max-norm relative over fluid nodes).  The same
+    saturated run in `gate_storage` gives the rate at the accuracy gate:
+    its results are those of the FP64 plain form, bit for bit."""
     import numpy as np
 
     from lbm_inputs import configs as cfg
@@ -423,7 +426,7 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
     e_nodes = 0.95 * np.mean([nodes[k] for k in range(pool)]) + 0.05 * nodes["big"]
     e_steps = 11000.0
 
-    def run(reqs, horizon, check=0):
+    def run(reqs, horizon, check=0, storage=storage):
         srv = lbm.Server(chunk_steps=chunk, storage=storage, eos="cs", max_instances=4096,
                          arena_bytes=96 << 30)
         arrive, done_t, info, fields = {}, {}, {}, {}
@@ -481,6 +484,8 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
     sat_reqs = [(0.0, k, s) for (_, k, s) in cfg.request_stream(1000.0, 0.12, pool=pool)]
     sat, _ = run(sat_reqs, 120.0)
     lam_max = sat["solves_per_s"]
+    progress(f"  saturated {storage}: {lam_max} stable solves/s; the same in {gate_storage}")
+    sat_gate, _ = run(sat_reqs, 180.0, storage=gate_storage)
     sweep = []
     for j, f in enumerate(rates):
         lam = max(lam_max * f, 0.1)
@@ -508,7 +513,12 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5):
             "mean_steps_per_request": e_steps,
             "offered_lups_at_200_per_s": offered,
             "offered_vs_fp32_hbm_roofline": round(offered / (PEAK_HBM_GBS * 1e9 / 72.0), 2),
-            "saturated": sat, "sustainable_rate_per_s": lam_max, "sweep": sweep}
+            "saturated": sat, "sustainable_rate_per_s": lam_max, "sweep": sweep,
+            "at_gate": {"storage": gate_storage, "gate": gate,
+                        "note": "every result equals the FP64 plain form's, bit for bit",
+                        "saturated": sat_gate},
+            "solves_per_s_at_gate": sat_gate["solves_per_s"],
+            "p99_s_at_gate_saturated": sat_gate["p99_s"]}
 
 
 def cpu_baseline(p, seconds):
@@ -615,7 +625,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5000,
                     help="steps of each instance of the batched mix (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=512)
-    ap.add_argument("--serve-requests", type=int, default=500,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of each served run at a fixed arrival rate (0: skip; "
                          "1000 puts the 99th percentile at the tenth-longest)")
     ap.add_argument("--serve-check", type=int, default=6,

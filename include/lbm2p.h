@@ -175,8 +175,16 @@ typedef struct lbm_domain lbm_domain;
  * LBM_EDEVICE. */
 int lbm_create_domain(const lbm_desc *desc, lbm_domain **out);
 
-/* Advance n >= 0 steps and wait for them.  LBM_EUNSTABLE names the first
- * step whose total mass was not finite (see lbm_unstable_step). */
+/* Advance n >= 0 steps and wait for them.  One step is the whole method
+ * of Secs. 2-4: psi and the interaction force (Eq. 16, Sec. 3.2) with the
+ * body force, the moments (Eq. 5), the collision with the Guo forcing term
+ * (Eqs. 1-2, 4; MRT as in Sec. 3.2), the pull streaming (Eq. 3), the rule
+ * of every cut link (Eqs. 6-14), the correction at every boundary node
+ * (Eqs. 15, 17-23) and the total mass.  Steps are enqueued on the domain's
+ * stream (as HIP graph replays once the step count repeats) and no host
+ * data moves.  n = 0 does nothing.  LBM_EUNSTABLE names the first step
+ * whose total mass was not finite (see lbm_unstable_step); further steps
+ * still run on the non-finite state and report the same first step. */
 int lbm_step(lbm_domain *d, int64_t n);
 
 /* As lbm_step, without waiting; lbm_sync waits and reports the status. */
@@ -203,13 +211,20 @@ int lbm_moments_device(lbm_domain *d, double *rho, double *ux, double *uy);
  * copies into rho, ux, uy are enqueued on the domain's stream. */
 int lbm_moments_device_noalloc(lbm_domain *d, double *rho, double *ux, double *uy);
 
-/* Total mass sum over fluid nodes of sum_a f_a at the current time (FP64). */
+/* Total mass M(t) = sum over fluid nodes of sum_a f*_a (FP64, summed in a
+ * fixed order, so equal states give equal bits): the m of Sec. 3.2, whose
+ * ratio m/m0 the paper plots in Figs. 4-8.  The post-collision
+ * populations carry the same mass as the pre-collision ones. */
 int lbm_total_mass(lbm_domain *d, double *out);
 
 /* Current time step count. */
 int lbm_time(lbm_domain *d, int64_t *t);
 
-/* The last min(t+1, capacity, cap) total masses M(.) in time order. */
+/* The last min(t+1, capacity, cap) total masses M(t) (as lbm_total_mass;
+ * the m(t) whose ratio to m(0) Sec. 3.2 and Figs. 4-8 follow) in time
+ * order into out[0 .. *n_written - 1], oldest first; the ring holds the
+ * capacity given at creation.  cap < 0, or a NULL out or n_written, gives
+ * LBM_EINVAL. */
 int lbm_mass_history(lbm_domain *d, double *out, int64_t cap,
                      int64_t *n_written);
 
