@@ -237,9 +237,10 @@ int lbm_unstable_step(lbm_domain *d, int64_t *step);
 int lbm_get_state(lbm_domain *d, void *buf, size_t *bytes);
 int lbm_set_state(lbm_domain *d, const void *buf, size_t bytes);
 
-/* Per-kernel timing: with every > 0, lbm_step brackets the boundary and
- * main launches of every every-th step with HIP events on the domain's
- * stream (no host synchronisation until 1024 samples are pending);
+/* Per-kernel timing: with every > 0, the boundary and main launches of
+ * every every-th step record their own start and end on HIP events of the
+ * domain's stream (the dispatch's timestamps, as a kernel profiler reads
+ * them; no host synchronisation until 1024 samples are pending);
  * lbm_kernel_times returns the summed durations (ms) and sample counts
  * since profiling was last set.  every = 0 switches it off. */
 int lbm_set_profiling(lbm_domain *d, int every);
@@ -265,7 +266,8 @@ int lbm_negative_rest(lbm_domain *d, int64_t *count);
  * evaluated inside the launch, so the populations cross HBM once per two
  * updates; the results are bit-identical to single steps.  Available for
  * the FP32 and FP16-deviation storage forms (not the FP16 per-node one),
- * periodic domains and every rule but Zhao-Yong (LBM_EINVAL otherwise);
+ * periodic domains, every rule but Zhao-Yong and link tables of fewer than
+ * 2^23 - 1 slots (LBM_EINVAL otherwise);
  * the default is 1.  tile_h is the two-step kernel's rows per workgroup
  * (0 = default 24, at least 4).  An odd step count ends with a
  * single step.  After a two-step pass the moments and the wall force of

@@ -37,6 +37,10 @@ struct Ctx {
     unsigned long long* negrest;
     unsigned long long* degen;
     int fix;
+    // when set, the main, two-step and boundary launches record their own
+    // start and end on these events (the dispatch's timestamps, without
+    // the launch latency that events recorded around a launch include)
+    hipEvent_t ev_start, ev_stop;
 };
 
 // one main pass src -> dst (or the moments of src when moments is set)

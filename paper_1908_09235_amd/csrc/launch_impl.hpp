@@ -1,6 +1,8 @@
 // Launcher bodies, instantiated once per storage precision.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "launch.hpp"
 
 namespace lbm {
@@ -8,6 +10,16 @@ namespace lbm {
 template <typename R>
 Phys<R> convert(const Phys<double>& d) {
     return phys_as<R>(d);
+}
+
+// A launch on c.stream, timed by the dispatch itself when c carries events.
+template <typename K, typename... A>
+void launch_on(const Ctx& c, K kernel, dim3 grid, dim3 block, A... args) {
+    if (c.ev_start)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, c.stream, c.ev_start, c.ev_stop, 0u,
+                              args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, c.stream, args...);
 }
 
 template <typename S, typename R, int EOS, bool MOM, int DEV, bool SAVEF>
@@ -31,8 +43,8 @@ void main_t(const Ctx& c, const S* src, S* dst) {
     a.nstrips = c.nstrips;
     a.side_mom_bytes = c.side_mom_bytes;
     a.side_f_bytes = c.side_f_bytes;
-    hipLaunchKernelGGL((k_main<S, R, EOS, MOM, DEV, SAVEF>), dim3(c.nblocks), dim3(c.tile_w), 0,
-                       c.stream, a, convert<R>(c.ph));
+    launch_on(c, k_main<S, R, EOS, MOM, DEV, SAVEF>, dim3(c.nblocks), dim3(c.tile_w), a,
+              convert<R>(c.ph));
 }
 
 template <typename S, typename R, bool MOM, int DEV, bool SAVEF>
@@ -77,8 +89,8 @@ void main2_t(const Ctx& c, const S* src, S* dst) {
     a.nsegs = c.nsegs2;
     a.nstrips = c.nstrips2;
     a.side_mom_bytes = c.side_mom_bytes;
-    hipLaunchKernelGGL((k_main2<S, R, EOS, DEV>), dim3(c.nblocks2), dim3(kF2Lanes), 0, c.stream,
-                       a, convert<R>(c.ph));
+    launch_on(c, k_main2<S, R, EOS, DEV>, dim3(c.nblocks2), dim3(kF2Lanes), a,
+              convert<R>(c.ph));
 }
 
 template <typename S, typename R, int DEV>
@@ -92,8 +104,7 @@ void main2_any(const Ctx& c, const void* src, void* dst) {
 
 template <typename S, int DEV = 0>
 void boundary_any(const Ctx& c, void* cur, const BndArgs& b, int nblocks) {
-    hipLaunchKernelGGL((k_boundary<S, DEV>), dim3(nblocks), dim3(256), 0, c.stream,
-                       static_cast<S*>(cur), b);
+    launch_on(c, k_boundary<S, DEV>, dim3(nblocks), dim3(256), static_cast<S*>(cur), b);
 }
 
 template <typename S, typename R>

@@ -173,9 +173,16 @@ Ctx ctx(lbm_domain* d) {
     return c;
 }
 
-void launch_main(lbm_domain* d, const void* src, void* dst, bool moments) {
-    if (d->storage == LBM_STORE_F64) launch_main_f64(ctx(d), src, dst, moments);
-    else launch_main_f32(ctx(d), src, dst, moments);
+// ev: optional start and end events that the launch records itself
+void launch_main(lbm_domain* d, const void* src, void* dst, bool moments,
+                 const hipEvent_t* ev = nullptr) {
+    Ctx c = ctx(d);
+    if (ev) {
+        c.ev_start = ev[0];
+        c.ev_stop = ev[1];
+    }
+    if (d->storage == LBM_STORE_F64) launch_main_f64(c, src, dst, moments);
+    else launch_main_f32(c, src, dst, moments);
 }
 
 int link_blocks(const lbm_domain* d) { return (d->nslot_links + 255) / 256; }
@@ -218,12 +225,17 @@ BndArgs bnd_args(lbm_domain* d) {
     return b;
 }
 
-void launch_boundary(lbm_domain* d, void* cur) {
+void launch_boundary(lbm_domain* d, void* cur, const hipEvent_t* ev = nullptr) {
     BndArgs b = bnd_args(d);
     // link blocks, then the open rows, then the block that reduces
     const int nbb = b.nlink_blocks + (d->open_x ? (d->ny + 255) / 256 : 0) + 1;
-    if (d->storage == LBM_STORE_F64) launch_boundary_f64(ctx(d), cur, b, nbb);
-    else launch_boundary_f32(ctx(d), cur, b, nbb);
+    Ctx c = ctx(d);
+    if (ev) {
+        c.ev_start = ev[0];
+        c.ev_stop = ev[1];
+    }
+    if (d->storage == LBM_STORE_F64) launch_boundary_f64(c, cur, b, nbb);
+    else launch_boundary_f32(c, cur, b, nbb);
     d->pending = false;
     d->force_valid = true;
 }
@@ -268,13 +280,19 @@ int harvest(lbm_domain* d) {
 void launch_pass(lbm_domain* d, bool two, hipEvent_t* rec) {
     void* cur = d->f[d->cur];
     void* nxt = d->f[d->cur ^ 1];
-    if (rec) (void)hipEventRecord(rec[0], d->stream);
-    launch_boundary(d, cur);
-    if (rec) (void)hipEventRecord(rec[1], d->stream);
-    if (rec) (void)hipEventRecord(rec[2], d->stream);
-    if (two) launch_main2_f32(ctx(d), cur, nxt);
-    else launch_main(d, cur, nxt, false);
-    if (rec) (void)hipEventRecord(rec[3], d->stream);
+    // with rec, each launch records its own start and end (rec[0..1]: the
+    // boundary pass, rec[2..3]: the main pass)
+    launch_boundary(d, cur, rec);
+    if (two) {
+        Ctx c = ctx(d);
+        if (rec) {
+            c.ev_start = rec[2];
+            c.ev_stop = rec[3];
+        }
+        launch_main2_f32(c, cur, nxt);
+    } else {
+        launch_main(d, cur, nxt, false, rec ? rec + 2 : nullptr);
+    }
     d->cur ^= 1;
     d->t += two ? 2 : 1;
     d->pending = true;
@@ -608,6 +626,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         if (used + len > 256) pad_to(lnode.size() + (256 - used));
         const int x = recs[k0].node % nx, y = recs[k0].node / nx;
         const int sb = slot_of(x, y);
+        // the two-step pass keeps (first link slot + 1) << 8 | flags in an int
+        if (lnode.size() + 1 >= (size_t(1) << 23)) d->fusable = false;
         node_link[pidx(x, y)] = (int)lnode.size() + 1;
         if (d->save_f) flags[pidx(x, y)] |= FL_SAVE_F;
         ++nb;
