@@ -27,12 +27,16 @@ def L():
 RUNS = (1, 2, 5, 37, 64, 3, 100)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_graph_replay_equals_plain_launches(L, storage):
+@pytest.mark.parametrize("storage,steps_per_pass", [("f64", 1), ("f32", 1), ("f32", 2)])
+def test_graph_replay_equals_plain_launches(L, storage, steps_per_pass):
     p = cfg.cfg1("mls", "B")
-    say(f"[gpu] graphs vs plain launches, cfg1 MLS+B {storage}, runs {RUNS}")
+    say(f"[gpu] graphs vs plain launches, cfg1 MLS+B {storage}, {steps_per_pass} step(s) "
+        f"per pass, runs {RUNS}")
     with L.Domain(p, storage=storage, history_capacity=512) as g, \
             L.Domain(p, storage=storage, history_capacity=512) as e:
+        if steps_per_pass == 2:
+            L.lbm_set_steps_per_pass(g.h, 2, 0)
+            L.lbm_set_steps_per_pass(e.h, 2, 0)
         L.lbm_set_profiling(e.h, 1)  # timed steps launch every kernel
         for n in RUNS:
             g.step(n)
@@ -45,8 +49,12 @@ def test_graph_replay_equals_plain_launches(L, storage):
         # them, a single step to finish an odd count
         steps, _ = L.lbm_get_steps_per_pass(e.h)
         passes = sum(n if steps == 1 else (n + 1) // 2 for n in RUNS)
-        _, cnt, _, _ = L.lbm_kernel_times(e.h)
-        assert cnt == passes
+        main_ms, cnt, bnd_ms, bcnt = L.lbm_kernel_times(e.h)
+        assert cnt == passes and bcnt == passes
+        # each launch recorded its own start and end: positive durations,
+        # far below a millisecond on a 128 x 128 lattice
+        say(f"    main {main_ms / cnt * 1e3:.2f} us, boundary {bnd_ms / bcnt * 1e3:.2f} us")
+        assert 0.0 < main_ms / cnt < 1.0 and 0.0 < bnd_ms / bcnt < 1.0
         assert np.array_equal(g.mass_history(), e.mass_history())
 
 
