@@ -950,8 +950,27 @@ struct BatchArgs {
     int persistent;                  // 1: tile queues, 0: one workgroup per tile
 };
 
-template <typename S>
-__device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long t, int tile_h) {
+// Tables that a launch only reads (the instance descriptors, states, tile
+// and link-block lists: written by the host, or by earlier launches), read
+// through the constant address space.  The compiler then loads them from a
+// uniform address with scalar loads into scalar registers, as it does the
+// kernel arguments; read through a generic pointer they come in as vector
+// loads (the launch's own stores might alias them) and every use needs a
+// v_readfirstlane.  The scalar cache is invalidated when a launch starts.
+// (The host pass of the compiler, which only checks these functions, has no
+// such address space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBM_CONST_AS __attribute__((address_space(4)))
+#else
+#define LBM_CONST_AS
+#endif
+template <typename T>
+__device__ __forceinline__ const LBM_CONST_AS T* ro(const T* p) {
+    return (const LBM_CONST_AS T*)p;
+}
+
+template <typename S, typename I_t>
+__device__ __forceinline__ MainArgs<S> inst_main_args(const I_t& I, long long t, int tile_h) {
     MainArgs<S> a;
     const int c = int(t & 1);
     a.src = static_cast<const S*>(I.f[c]);
@@ -978,12 +997,13 @@ __device__ __forceinline__ MainArgs<S> inst_main_args(const BInst& I, long long 
 template <typename S, typename R, int EOS, int DEV, bool SAVEF, int RING>
 __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
     g = __builtin_amdgcn_readfirstlane(g);
-    const int2 te = b.tiles[g];
-    const BState st = b.state[te.x];
+    const int2 te = ro(b.tiles)[g];
+    const BState st = ro<BState>(b.state)[te.x];
     if (st.remaining <= 0) return;
-    const BInst& I = b.inst[te.x];
+    const auto& I = ro(b.inst)[te.x];
+    const Phys<double> ph = I.ph;
     main_tile<S, R, EOS, false, DEV, SAVEF, RING>(inst_main_args<S>(I, st.t, b.tile_h),
-                                                  phys_as<R>(I.ph), te.y);
+                                                  phys_as<R>(ph), te.y);
 }
 
 // Persistent form: a fixed grid; each workgroup takes tiles from the queue
@@ -992,9 +1012,8 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& b, int g) {
 // contiguous runs of the tile list, so one XCD works through compact
 // pieces of the same instances and finds their halos in its L2.
 template <typename S, typename R, int EOS, int DEV, bool SAVEF, int RING>
-// (three wavefronts per SIMD: the instance arguments add registers to the
-// tile's, and the benchmark's form would otherwise need one more than three
-// wavefronts leave)
+// (at least three wavefronts per SIMD: a ring of four rows would otherwise
+// take more registers than three leave)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_main_batch(
     BatchArgs b) {
     if (!b.persistent) {
@@ -1028,12 +1047,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 template <typename S, int DEV>
 __global__ __launch_bounds__(256) void k_boundary_batch(BatchArgs b) {
-    const int n = *b.nlblk;
+    const int n = *ro(b.nlblk);
     for (int k = blockIdx.x; k < n; k += gridDim.x) {
-        const int2 e = b.lblk[k];
-        const BState st = b.state[e.x];
+        const int2 e = ro(b.lblk)[k];
+        const BState st = ro<BState>(b.state)[e.x];
         if (st.remaining <= 0) continue;
-        const BInst& I = b.inst[e.x];
+        const auto& I = ro(b.inst)[e.x];
         BndArgs a;
         a.nslot = I.nslot;
         a.lnode = I.lnode;
@@ -1080,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
         BState* st = b.state + i;
         const long long rem = st->remaining;
         if (rem <= 0) continue;
-        const BInst& I = b.inst[i];
+        const auto& I = ro(b.inst)[i];
         const long long t1 = st->t + 1;
         __syncthreads();
         reduce_partials(I.partial, I.np, I.hist, t1 % I.cap, t1, I.unstable);
