@@ -427,8 +427,13 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5,
     e_steps = 11000.0
 
     def run(reqs, horizon, check=0, storage=storage):
+        # one workgroup per tile, 256 x 8 tiles, rings of four rows: the
+        # shape the autotuner picks for the FP32 batched mix, and the
+        # fastest of those measured on the saturated request mix (its 2048^2
+        # requests carry half of the work, and one large instance runs
+        # twice as long per step from the persistent queue)
         srv = lbm.Server(chunk_steps=chunk, storage=storage, eos="cs", max_instances=4096,
-                         arena_bytes=96 << 30)
+                         arena_bytes=96 << 30, persistent=0, tile_w=256, tile_h=8, ring=4)
         arrive, done_t, info, fields = {}, {}, {}, {}
         i = 0
         t0 = time.perf_counter()
@@ -509,6 +514,7 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5,
     offered = 200.0 * e_nodes * e_steps
     return {"workload": "droplet_cylinder_requests", "storage": storage,
             "chunk_steps": chunk, "pool": pool,
+            "launch": {"persistent": 0, "tile_w": 256, "tile_h": 8, "ring": 4},
             "mean_nodes_per_request": round(float(e_nodes)),
             "mean_steps_per_request": e_steps,
             "offered_lups_at_200_per_s": offered,
