@@ -453,7 +453,7 @@ int lbm_batch_create(const lbm_batch_desc* bd, lbm_batch** out) {
     int rc = b->arena.init((size_t)bd->arena_bytes);
     if (!rc) rc = dmalloc(&b->d_inst, n);
     if (!rc) rc = dmalloc(&b->d_state, n);
-    if (!rc) rc = dmalloc(&b->d_qnext, kQueues);
+    if (!rc) rc = dmalloc(&b->d_qnext, kQueues * kQueueStride);
     if (!rc) rc = dmalloc(&b->d_qbound, kQueues + 1);
     if (!rc) rc = dmalloc(&b->d_nlblk, 1);
     if (!rc) rc = hmalloc(&b->h_inst, n);
@@ -464,7 +464,7 @@ int lbm_batch_create(const lbm_batch_desc* bd, lbm_batch** out) {
         free_batch(b);
         return rc;
     }
-    if (hipMemsetAsync(b->d_qnext, 0, kQueues * sizeof(int), b->stream) != hipSuccess ||
+    if (hipMemsetAsync(b->d_qnext, 0, kQueues * kQueueStride * sizeof(int), b->stream) != hipSuccess ||
         hipMemsetAsync(b->d_state, 0, n * sizeof(BState), b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         free_batch(b);

@@ -937,11 +937,17 @@ struct BState {
     long long remaining;
 };
 
+// Ints between two queue heads of the persistent form: each head on a
+// line of its own, so that the tickets of different queues (taken with
+// device-scope atomics, which the XCDs' L2 caches do not hold) do not queue
+// up on one line.
+constexpr int kQueueStride = 64;
+
 struct BatchArgs {
     const BInst* __restrict__ inst;
     BState* __restrict__ state;
     const int2* __restrict__ tiles;  // (instance, tile) in queue order
-    int* __restrict__ qnext;         // [8] queue heads, zeroed by the reduce pass
+    int* __restrict__ qnext;         // 8 queue heads kQueueStride apart, zeroed by the reduce pass
     const int* __restrict__ qbound;  // [9]: queue k holds tiles [qbound[k], qbound[k+1])
     const int2* __restrict__ lblk;   // (instance, link block)
     const int* __restrict__ nlblk;   // number of link blocks
@@ -1029,7 +1035,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             int g = -1;
             while (qi < 8) {
                 const int q = (xcd + qi) & 7;
-                const int k = b.qbound[q] + atomicAdd(&b.qnext[q], 1);
+                const int k = b.qbound[q] + atomicAdd(&b.qnext[q * kQueueStride], 1);
                 if (k < b.qbound[q + 1]) {
                     g = k;
                     break;
@@ -1108,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
             st->remaining = *I.unstable >= 0 ? 0 : rem - 1;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x < 8) b.qnext[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 8) b.qnext[threadIdx.x * kQueueStride] = 0;
 }
 
 }  // namespace lbm
