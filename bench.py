@@ -429,9 +429,7 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5,
     def run(reqs, horizon, check=0, storage=storage):
         # one workgroup per tile, 256 x 8 tiles, rings of four rows: the
         # shape the autotuner picks for the FP32 batched mix, and the
-        # fastest of those measured on the saturated request mix (its 2048^2
-        # requests carry half of the work, and one large instance runs
-        # twice as long per step from the persistent queue)
+        # fastest of those measured on the saturated request mix
         srv = lbm.Server(chunk_steps=chunk, storage=storage, eos="cs", max_instances=4096,
                          arena_bytes=96 << 30, persistent=0, tile_w=256, tile_h=8, ring=4)
         arrive, done_t, info, fields = {}, {}, {}, {}
