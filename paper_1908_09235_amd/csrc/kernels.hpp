@@ -678,6 +678,10 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
     const int ic = i < b.nslot ? i : 0;
     const int node_r = b.lnode[ic], slotb = b.lslotb[ic], slotf = b.lslotf[ic];
     const int xf = b.lxf[ic], xff = b.lxff[ic];
+    // the ghost slot too (and, per-node references, the node whose density
+    // encodes it), so that the final store waits for no load of its own
+    const int ghost = b.lghost[ic];
+    const int gref = DEV == 2 ? b.lref[ic] : 0;
     double c[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) c[k] = b.lc[8 * ic + k];
@@ -741,12 +745,12 @@ __device__ __forceinline__ void boundary_block(S* __restrict__ A, const BndArgs&
         __syncthreads();
     }
     if (active) {
-        const int g = b.lghost[i];
+        const int g = ghost;
         double enc = DEV == 1 ? wt(d) * b.rref : 0.0;
         if constexpr (DEV == 2) {
             // every link into ghost g encodes against the same density: that
             // of one boundary node next to it, which one of them records
-            const float rg = float(b.side_mom[3 * b.lref[i]]);
+            const float rg = float(b.side_mom[3 * gref]);
             if ((meta >> 16) & 1) rpl[g] = rg;
             enc = wt(d) * double(rg);
         }
