@@ -10,10 +10,11 @@ Prints one JSON line: MLUPS over fluid nodes (whole job) of the plain form
 with FP32 populations (FP64 arithmetic), the roofline of the main kernel
 (achieved HBM GB/s from its algorithmic bytes and its mean launch duration,
 timed with HIP events on its stream), the FP64-storage and FP32-arithmetic
-forms of the same workload, the precision forms on 8192 x 4096, the
-batched form (FP32 storage, and the same mix in FP64 storage) and the
-served form, the paper's other experiments (flow past a
-cylinder, gravity q-sweep, contact angle), and the CPU oracle timed on a
+forms of the same workload, the precision forms on 8192 x 4096, two
+time steps per pass against one, the batched form (FP32 storage, and the
+same mix in FP64 storage) and the served form, the paper's other
+experiments (flow past a cylinder, gravity q-sweep, contact angle), and
+the CPU oracle timed on a
 bounded sample (one copy, then one independent copy per usable core at
 once, before the GPU is touched).
 """
@@ -525,6 +526,59 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5,
             "p99_s_at_gate_saturated": sat_gate["p99_s"]}
 
 
+def two_step_leg(steps, warmup, stream, prof_steps):
+    """Two time steps per pass against one.  Cases: the wall-free shear wave
+    (2048 x 2048, BGK, no interaction force) in FP32 storage with FP32 and
+    with FP64 arithmetic, and the benchmark's workload.  Per case and
+    setting: the step rate over `steps` timed steps (graph replays), and the
+    mean duration of the main launch over a separate pass of `prof_steps`
+    steps (each launch records its own start and end).  The effective rate
+    counts the algorithmic bytes of the steps one launch advances, 18
+    populations per fluid node per step, against the HBM peak."""
+    import torch
+
+    from lbm_inputs import configs as cfg
+    from paper_1908_09235_amd import lbm
+
+    cases = [("shear_wave_2048x2048_bgk", cfg.shear_wave(2048, nx=2048, collision="bgk"),
+              ("f32_arith32", "f32")),
+             ("droplet_cylinder_2048x2048_mrt_mls_B", cfg.cfg2a(), ("f32",))]
+    out = {}
+    for name, p, storages in cases:
+        fluid = int((~p.solid.astype(bool)).sum())
+        for st in storages:
+            rec = {}
+            for spp in (1, 2):
+                d = lbm.Domain(p, storage=st, stream=stream, history_capacity=1 << 12)
+                if spp == 2:
+                    lbm.lbm_set_steps_per_pass(d.h, 2, 0)
+                d.step(warmup)  # also captures the step graphs
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lbm.lbm_step_async(d.h, steps)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+                lbm.lbm_sync(d.h)
+                lbm.lbm_set_profiling(d.h, 1)
+                lbm.lbm_step(d.h, prof_steps)
+                mm, mn, bm, bn = lbm.lbm_kernel_times(d.h)
+                lbm.lbm_set_profiling(d.h, 0)
+                d.close()
+                main_ms = mm / max(mn, 1)
+                alg = spp * 18 * BYTES_PER_POP[st] * fluid
+                gbs = alg / (main_ms * 1e-3) / 1e9 if main_ms > 0 else None
+                rec[f"steps_per_pass_{spp}"] = {
+                    "us_per_step": round(sec / steps * 1e6, 2),
+                    "mlups": round(fluid * steps / sec / 1e6, 1),
+                    "main_launch_us": round(main_ms * 1e3, 2),
+                    "boundary_launch_us": round(bm / max(bn, 1) * 1e3, 2),
+                    "algorithmic_bytes_per_launch": alg,
+                    "effective_gbs": gbs and round(gbs, 1),
+                    "frac": gbs and round(gbs / PEAK_HBM_GBS, 4)}
+            out[f"{name}:{st}"] = rec
+    return out
+
+
 def cpu_baseline(p, seconds):
     from oracle import core as ora
 
@@ -626,6 +680,8 @@ def main():
                     help="steps between the precision forms' error checks")
     ap.add_argument("--precision-time-steps", type=int, default=500,
                     help="steps each precision form is timed over")
+    ap.add_argument("--two-step-steps", type=int, default=2000,
+                    help="steps of each two-steps-per-pass comparison (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5000,
                     help="steps of each instance of the batched mix (0: skip)")
     ap.add_argument("--batch-instances", type=int, default=512)
@@ -712,6 +768,11 @@ def main():
         prec = precision_leg(a.precision_steps, a.warmup, stream, a.prof_steps,
                              a.precision_check, a.precision_time_steps)
 
+    two = None
+    if a.two_step_steps > 0:
+        progress("two steps per pass against one, 2048^2")
+        two = two_step_leg(a.two_step_steps, a.warmup, stream, a.prof_steps)
+
     batch = None
     if a.batch_steps > 0:
         progress(f"batched mix, {a.batch_instances} instances")
@@ -751,6 +812,7 @@ def main():
         "cpu_baseline": cpu,
         "also": also,
         "precision": prec,
+        "two_step": two,
         "batched": batch,
         "served": serve,
         "paper_experiments": other,
