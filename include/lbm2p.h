@@ -266,8 +266,9 @@ int lbm_negative_rest(lbm_domain *d, int64_t *count);
  * evaluated inside the launch, so the populations cross HBM once per two
  * updates; the results are bit-identical to single steps.  Available for
  * the FP32 and FP16-deviation storage forms (not the FP16 per-node one),
- * periodic domains, every rule but Zhao-Yong and link tables of fewer than
- * 2^23 - 1 slots (LBM_EINVAL otherwise);
+ * periodic domains, every rule but Zhao-Yong and the quadratic
+ * interpolation, and link tables of fewer than 2^23 - 1 slots (LBM_EINVAL
+ * otherwise);
  * the default is 1.  tile_h is the two-step kernel's rows per workgroup
  * (0 = default 24, at least 4).  An odd step count ends with a
  * single step.  After a two-step pass the moments and the wall force of

@@ -15,12 +15,16 @@
 // strip of 56 columns (lane j holds column x0 - 4 + j; the four columns
 // on either side only feed the strip's interior) and marches upward
 // through the rows of its segment.  Per row it pulls f(t + 1) from HBM (two
-// rows of loads in flight, as in the single-step kernel), forms psi(t + 1),
-// collides step t + 1 two rows behind into LDS rings of f*(t + 1) and of
-// the moments of t + 1, evaluates the wall rules of the boundary nodes two
-// rows further behind, pulls f(t + 2) from the ring, forms psi(t + 2) and
-// collides step t + 2 one row later, storing f*(t + 2) of the strip's own
-// columns and rows.  Row k of the march is absolute row y0 - 3 + k.
+// rows of loads in flight, as in the single-step kernel) and forms
+// psi(t + 1); collides step t + 1 one row behind into LDS rings of three
+// rows of f*(t + 1), of the moments of t + 1 and of the flags; evaluates
+// the wall rules of the boundary nodes of the row before that, pulls its
+// f(t + 2) from the ring and forms psi(t + 2); and collides step t + 2 one
+// row later still, storing f*(t + 2) of the strip's own columns and rows.
+// Row k of the march is absolute row y0 - 3 + k.  The three-row rings keep
+// the LDS per wavefront small enough for more wavefronts per CU; the
+// quadratic interpolation rule, which reads a fluid node two rows from the
+// boundary node (x_ff), falls outside them and is not fused.
 #pragma once
 
 #include "kernels.hpp"
@@ -72,7 +76,10 @@ struct Pull2 {
 template <typename S, typename R, int EOS, int DEV>
 __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) {
     static_assert(DEV == 0 || DEV == 1, "per-node references are not fused");
-    constexpr int N1 = 5, NM = 4;  // ring rows: f*(t + 1), moments of t + 1
+    // ring rows of f*(t + 1), of the moments of t + 1 and of the flags: the
+    // rows m - 1 .. m + 1 around the row m being pulled, the newest being
+    // the row just collided
+    constexpr int N1 = 3, NM = 3;
     __shared__ S fs1[N1][9][kF2Lanes];
     __shared__ double mo1[NM][3][kF2Lanes];
     __shared__ R ps1[3][kF2Lanes];
@@ -121,10 +128,10 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
     // ---- step t + 1: loads, psi, collision (as main_tile)
     uint8_t nfl;
     auto load_flags = [&](int k) { nfl = bload<uint8_t>(rfl, x, (unsigned)row_of(k) * pitch); };
-    // pulled rows -1 .. H + 6 feed psi(t + 1); later ones move nothing
+    // pulled rows 0 .. H + 5 feed psi(t + 1); later ones move nothing
     auto issue = [&](int k, Row2Load<S>& L) {
         const int y = row_of(k);
-        const bool rv = k <= H + 6;
+        const bool rv = k <= H + 5;
         const uint8_t fl = rv ? nfl : uint8_t(FL_SOLID);
         L.fl = fl;
         load_flags(k + 1);
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
     };
 
     double msum1 = 0.0, msum2 = 0.0;
-    Pull2<S> fcur{}, fnxt{};      // pulled f(t + 2) of rows k - 3 and k - 2
+    Pull2<S> fcur{}, fnxt{};      // pulled f(t + 2) of rows k - 2 and k - 1
 
     // the wall rules of step t + 2 for the boundary node of lane j in row m
     // (march index), applied to its pulled populations f
@@ -210,7 +217,9 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
                                   switch (what) {
                                   case LV_OD_B: return fst(od, m, j);
                                   case LV_D_F: return fst(d, m - dy, j - dx);
-                                  case LV_D_FF: return fst(d, m - 2 * dy, j - 2 * dx);
+                                  // (x_ff lies two rows away, outside the
+                                  // ring: the quadratic rule is not fused)
+                                  case LV_D_FF: return NAN;
                                   case LV_OD_F: return fst(od, m - dy, j - dx);
                                   case LV_UFX: return mo1[rm(m - dy)][1][lane(j - dx)];
                                   case LV_UFY: return mo1[rm(m - dy)][2][lane(j - dx)];
@@ -267,13 +276,13 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
     };
 
     // row k of the march: psi(t + 1) of row k + 1; step t + 1 of row k;
-    // wall rules, pull and psi of step t + 2 of row k - 2; step t + 2 of
-    // row k - 3; then the loads of row k + 3 into Lc
+    // wall rules, pull and psi of step t + 2 of row k - 1; step t + 2 of
+    // row k - 2; then the loads of row k + 3 into Lc
     auto step = [&](int k, Row2Load<S>& Lc, Row2Load<S>& Ln) {
         publish1(Ln, k + 1);
         __syncthreads();
-        // -- step t + 1, row k (absolute rows y0 - 3 .. y0 + H + 2)
-        if (k <= H + 5) {
+        // -- step t + 1, row k (absolute rows y0 - 2 .. y0 + H + 1)
+        if (k <= H + 4) {
             const bool fluid = !(Lc.fl & FL_SOLID);
             R fc[9];
             decode(Lc.f, fc);
@@ -296,9 +305,9 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
             msi[rm(k)][j] = Lc.si;
         }
         __syncthreads();
-        // -- step t + 2: wall rules, pull and psi of row m = k - 2
+        // -- step t + 2: wall rules, pull and psi of row m = k - 1
         // (absolute rows y0 - 1 .. y0 + H)
-        const int m = k - 2;
+        const int m = k - 1;
         if (m >= 2 && m <= H + 3) {
             const int mf = mfl[rm(m)][j];
             const bool fluid = !(mf & FL_SOLID);
@@ -311,8 +320,8 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
             ps2[r3(m)][j] = fluid ? psi_of<EOS, R>(rho, ph) : R(mo1[rm(m)][0][j]);
         }
         __syncthreads();
-        // -- step t + 2, row n = k - 3 (absolute rows y0 .. y0 + H - 1)
-        const int n = k - 3;
+        // -- step t + 2, row n = k - 2 (absolute rows y0 .. y0 + H - 1)
+        const int n = k - 2;
         if (n >= 3 && n < H + 3) {
             const int nf = mfl[rm(n)][j];
             const bool live = outc && !(nf & FL_SOLID);
@@ -343,16 +352,16 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
     };
 
     Row2Load<S> A, B, C;
-    load_flags(-1);
-    issue(-1, C);
-    issue(0, A);
-    issue(1, B);
-    publish1(C, -1);
-    issue(2, C);
-    publish1(A, 0);
-    // a whole number of three-row rotations over rows 0 .. H + 5
-    const int K3 = (H + 6 + 2) / 3 * 3;
-    for (int k = 0; k < K3; k += 3) {
+    load_flags(0);
+    issue(0, C);
+    issue(1, A);
+    issue(2, B);
+    publish1(C, 0);
+    issue(3, C);
+    publish1(A, 1);
+    // a whole number of three-row rotations over rows 1 .. H + 4
+    const int K3 = (H + 4 + 2) / 3 * 3;
+    for (int k = 1; k < 1 + K3; k += 3) {
         step(k, A, B);
         step(k + 1, B, C);
         step(k + 2, C, A);

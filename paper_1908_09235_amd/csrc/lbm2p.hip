@@ -569,11 +569,14 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     d->nblocks = d->nstrips * d->nsegs;
     // two steps per pass: FP32 or FP16 populations with one reference
     // density, periodic, any rule but Zhao-Yong (which needs the
-    // pre-collision populations of the intermediate step); not for the
-    // instances of a batch, which run the batched kernels
+    // pre-collision populations of the intermediate step) and the
+    // quadratic interpolation (whose second fluid node lies outside the
+    // pass's three-row rings); not for the instances of a batch, which run
+    // the batched kernels
     d->fusable = (s->storage == LBM_STORE_F32 || s->storage == LBM_STORE_F32_ARITH32 ||
                   s->storage == LBM_STORE_F32DEV || s->storage == LBM_STORE_F16DEV) &&
-                 !s->open_x && s->rule != LBM_RULE_ZHAO_YONG && !d->arena;
+                 !s->open_x && s->rule != LBM_RULE_ZHAO_YONG &&
+                 s->rule != LBM_RULE_IBB_QUADRATIC && !d->arena;
     d->fused = 1;  // two steps per pass on request (lbm_set_steps_per_pass)
     d->tile_h2 = kTileH2;
     d->nstrips2 = (nx + kF2Cols - 1) / kF2Cols;

@@ -31,7 +31,6 @@ def _cases():
     return {
         "cfg1_mls_B": lambda: cfg.cfg1("mls", "B"),
         "cfg1_mls_A": lambda: cfg.cfg1("mls", "A"),
-        "cfg1_ibbq_A": lambda: cfg.cfg1("ibb_quadratic", "A"),
         "cfg1_ibbl_none": lambda: cfg.cfg1("ibb_linear", "none"),
         "cfg1_halfway": lambda: cfg.cfg1("halfway", "none"),
         "cfg1_mls_bao": lambda: cfg.cfg1("mls", "bao"),
@@ -141,7 +140,8 @@ def test_two_step_checkpoint_resumes(L):
 
 
 def test_two_steps_refused_where_not_available(L):
-    for p, st in ((cfg.cfg1("zhao_yong", "A"), "f32"), (cfg.cfg1("mls", "B"), "f64"),
+    for p, st in ((cfg.cfg1("zhao_yong", "A"), "f32"), (cfg.cfg1("ibb_quadratic", "A"), "f32"),
+                  (cfg.cfg1("mls", "B"), "f64"),
                   (cfg.cfg1("mls", "B"), "f16node")):
         with L.Domain(p, storage=st) as d:
             assert L.lbm_get_steps_per_pass(d.h)[0] == 1
