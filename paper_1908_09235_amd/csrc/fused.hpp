@@ -81,7 +81,10 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
     // the row just collided
     constexpr int N1 = 3, NM = 3;
     __shared__ S fs1[N1][9][kF2Lanes];
-    __shared__ double mo1[NM][3][kF2Lanes];
+    // moments of t + 1 in the arithmetic type: rho (its deviation from the
+    // reference density with one reference; psi of the wall density at a
+    // solid node), u_x, u_y -- the wall rules widen them to FP64 exactly
+    __shared__ R mo1[NM][3][kF2Lanes];
     __shared__ R ps1[3][kF2Lanes];
     __shared__ R ps2[3][kF2Lanes];
     // per lane and ring row: flags | (first link slot + 1) << 8, and the
@@ -199,7 +202,9 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
             const double v = double(fs1[r1(row)][q][lane(l)]);
             return DEV == 1 ? v + wt(q) * double(ph.rref) : v;
         };
-        const double rho_b = mo1[rm(m)][0][j], ubx = mo1[rm(m)][1][j], uby = mo1[rm(m)][2][j];
+        const double m0 = double(mo1[rm(m)][0][j]);
+        const double rho_b = DEV == 1 ? double(ph.rref) + m0 : m0;
+        const double ubx = double(mo1[rm(m)][1][j]), uby = double(mo1[rm(m)][2][j]);
         const int i0 = bnd ? nl - 1 : 0;
         const int len = bnd ? (a.lmeta[i0] >> 8) & 15 : 0;
         auto eval = [&](int i, double& fab, double& ch, double& bk, double& wl, int& d) {
@@ -221,8 +226,8 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
                                   // ring: the quadratic rule is not fused)
                                   case LV_D_FF: return NAN;
                                   case LV_OD_F: return fst(od, m - dy, j - dx);
-                                  case LV_UFX: return mo1[rm(m - dy)][1][lane(j - dx)];
-                                  case LV_UFY: return mo1[rm(m - dy)][2][lane(j - dx)];
+                                  case LV_UFX: return double(mo1[rm(m - dy)][1][lane(j - dx)]);
+                                  case LV_UFY: return double(mo1[rm(m - dy)][2][lane(j - dx)]);
                                   default: return 0.0;  // LV_PRE: Zhao-Yong is not fused
                                   }
                               });
@@ -298,9 +303,9 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
 #pragma unroll
             for (int q = 0; q < 9; ++q) fs1[s][q][j] = fluid ? S(fc[q] + dh[q]) : S(0);
             // (a solid node keeps psi of its wall density in the density slot)
-            mo1[rm(k)][0][j] = fluid ? rho_d : double(psi_w(Lc));
-            mo1[rm(k)][1][j] = fluid ? double(ux) : 0.0;
-            mo1[rm(k)][2][j] = fluid ? double(uy) : 0.0;
+            mo1[rm(k)][0][j] = fluid ? (DEV == 1 ? drho : rho) : psi_w(Lc);
+            mo1[rm(k)][1][j] = fluid ? ux : R(0);
+            mo1[rm(k)][2][j] = fluid ? uy : R(0);
             mfl[rm(k)][j] = int(Lc.fl) | (Lc.nl << 8);
             msi[rm(k)][j] = Lc.si;
         }
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
             R f[9];
             decode(fnxt.f, f);
             const R rho = DEV == 1 ? ph.rref + dens<R>(f) : dens<R>(f);
-            ps2[r3(m)][j] = fluid ? psi_of<EOS, R>(rho, ph) : R(mo1[rm(m)][0][j]);
+            ps2[r3(m)][j] = fluid ? psi_of<EOS, R>(rho, ph) : mo1[rm(m)][0][j];
         }
         __syncthreads();
         // -- step t + 2, row n = k - 2 (absolute rows y0 .. y0 + H - 1)
