@@ -529,7 +529,9 @@ def serve_leg(storage, n_requests, rates, chunk, pool, n_check, gate=1e-5,
 def two_step_leg(steps, warmup, stream, prof_steps):
     """Two time steps per pass against one.  Cases: the wall-free shear wave
     (2048 x 2048, BGK, no interaction force) in FP32 storage with FP32 and
-    with FP64 arithmetic, and the benchmark's workload.  Per case and
+    with FP64 arithmetic, the benchmark's workload, and the 96 cylinders of
+    the precision forms (8192 x 4096) with FP32 arithmetic, in FP32 storage
+    and as FP32 deviations.  Per case and
     setting: the step rate over `steps` timed steps (graph replays), and the
     mean duration of the main launch over a separate pass of `prof_steps`
     steps (each launch records its own start and end).  The effective rate
@@ -540,11 +542,13 @@ def two_step_leg(steps, warmup, stream, prof_steps):
     from lbm_inputs import configs as cfg
     from paper_1908_09235_amd import lbm
 
-    cases = [("shear_wave_2048x2048_bgk", cfg.shear_wave(2048, nx=2048, collision="bgk"),
+    cases = [("shear_wave_2048x2048_bgk", lambda: cfg.shear_wave(2048, nx=2048, collision="bgk"),
               ("f32_arith32", "f32")),
-             ("droplet_cylinder_2048x2048_mrt_mls_B", cfg.cfg2a(), ("f32",))]
+             ("droplet_cylinder_2048x2048_mrt_mls_B", cfg.cfg2a, ("f32",)),
+             ("cylinders96_8192x4096_bgk_mls_B", cfg.many_cylinders, ("f32_arith32", "f32dev"))]
     out = {}
-    for name, p, storages in cases:
+    for name, make, storages in cases:
+        p = make()
         fluid = int((~p.solid.astype(bool)).sum())
         for st in storages:
             rec = {}
@@ -770,7 +774,7 @@ def main():
 
     two = None
     if a.two_step_steps > 0:
-        progress("two steps per pass against one, 2048^2")
+        progress("two steps per pass against one")
         two = two_step_leg(a.two_step_steps, a.warmup, stream, a.prof_steps)
 
     batch = None
