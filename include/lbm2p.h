@@ -270,7 +270,7 @@ int lbm_negative_rest(lbm_domain *d, int64_t *count);
  * interpolation, and link tables of fewer than 2^23 - 1 slots (LBM_EINVAL
  * otherwise);
  * the default is 1.  tile_h is the two-step kernel's rows per workgroup
- * (0 = default 24, at least 4).  An odd step count ends with a
+ * (0 = default 16, at least 4).  An odd step count ends with a
  * single step.  After a two-step pass the moments and the wall force of
  * the last step come from a replay of the intermediate step, in buffers
  * held since creation. */

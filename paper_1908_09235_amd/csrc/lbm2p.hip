@@ -19,7 +19,7 @@ namespace {
 
 constexpr uint64_t kStateMagic = 0x6c626d3270737431ULL;  // "lbm2pst1"
 constexpr int kProfPool = 1024;
-constexpr int kTileH2 = 24;     // rows per segment of the two-step kernel
+constexpr int kTileH2 = 16;     // rows per segment of the two-step kernel
 constexpr int kMinTileH2 = 4;
 
 }  // namespace
