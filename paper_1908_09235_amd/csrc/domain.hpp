@@ -77,6 +77,8 @@ struct lbm_domain {
     bool fusable = false;
     int tile_h2 = 0, nstrips2 = 0, nsegs2 = 0, nblocks2 = 0;
     int* node_link = nullptr;    // per node (pitch layout): first link slot + 1, or 0
+    int* tile_order = nullptr;   // tile of each workgroup of the two-step pass
+    std::vector<int> bnd_x, bnd_y;  // host: the boundary nodes (tile weights)
     double* partial2 = nullptr;  // masses of the second step of a pass
     int pending_steps = 0;       // steps of the last pass whose masses are pending
     // After a two-step pass f*(t - 1) is not in memory: the buffer that

@@ -42,6 +42,7 @@ struct Main2Args {
     const uint8_t* __restrict__ flags;
     const int* __restrict__ side_idx;     // per node (pitch layout), flagged only
     const int* __restrict__ node_link;    // per node: first link slot + 1, or 0
+    const int* __restrict__ order;        // tile of each workgroup (null: XCD order)
     const float* __restrict__ psiw;       // FP16 storage: psi_w of solid nodes
     double* __restrict__ side_mom;        // moments of t + 2 of flagged nodes
     double* __restrict__ partial1;        // per workgroup: mass at t + 1
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) 
     const rsrc_t rpw = make_rsrc(a.psiw, ES == 2 ? pitch * (unsigned)a.ny * 4u : 0u);
 
     const int j = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = a.order ? a.order[blockIdx.x] : xcd_tile(blockIdx.x, gridDim.x);
     const int seg = tile / a.nstrips, strip = tile - seg * a.nstrips;
     const int x0 = (int)(((unsigned long long)strip * (unsigned)a.nx) / (unsigned)a.nstrips);
     const int ncols =

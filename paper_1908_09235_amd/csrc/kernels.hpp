@@ -40,7 +40,7 @@ enum : uint8_t { FL_SOLID = 1, FL_SAVE_MOM = 2, FL_SAVE_F = 4 };
 // rows), so that the workgroups that run together on one XCD cover a
 // compact block of the lattice and find each other's halo rows and columns
 // in that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
+__host__ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int xcd = b & 7, idx = b >> 3;
     const int q = nb >> 3, r = nb & 7;
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;

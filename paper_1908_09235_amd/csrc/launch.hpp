@@ -30,6 +30,7 @@ struct Ctx {
     // two steps per pass (k_main2)
     int tile_h2, nsegs2, nstrips2, nblocks2;
     const int* node_link;
+    const int* tile_order;  // two-step pass: tile of each workgroup
     double* partial2;
     const int* lmeta;
     const double* lc;

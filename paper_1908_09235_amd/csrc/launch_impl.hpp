@@ -71,6 +71,7 @@ void main2_t(const Ctx& c, const S* src, S* dst) {
     a.flags = c.flags;
     a.side_idx = c.side_idx;
     a.node_link = c.node_link;
+    a.order = c.tile_order;
     a.psiw = c.psiw;
     a.side_mom = c.side_mom;
     a.partial1 = c.partial;

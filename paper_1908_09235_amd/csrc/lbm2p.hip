@@ -163,6 +163,7 @@ Ctx ctx(lbm_domain* d) {
     c.nstrips2 = d->nstrips2;
     c.nblocks2 = d->nblocks2;
     c.node_link = d->node_link;
+    c.tile_order = d->tile_order;
     c.partial2 = d->partial2;
     c.lmeta = d->lmeta;
     c.lc = d->lc;
@@ -422,6 +423,50 @@ int check_unstable(lbm_domain* d) {
     return u >= 0 ? LBM_EUNSTABLE : LBM_OK;
 }
 
+// Dispatch order of the two-step pass's tiles: the tiles whose strip and
+// rows hold the most boundary nodes first, the others in the XCD order of
+// xcd_tile.  A tile that evaluates wall rules in many of its rows lasts
+// several times as long as one without walls; started last, such tiles
+// would leave the launch waiting on a few of them.  A tile's weight is the
+// number of boundary nodes in the rows whose wall rules it evaluates
+// (y0 - 1 .. y0 + H) and the 64 columns of its wavefront (x0 - 4 ..
+// x0 + 59).  Only the order changes: every tile writes its own partials.
+int order_tiles(lbm_domain* d) {
+    if (!d->tile_order) return LBM_OK;
+    const int ns = d->nstrips2, ng = d->nsegs2, n = d->nblocks2, H = d->tile_h2;
+    const int nx = d->nx, ny = d->ny;
+    std::vector<long long> w((size_t)n, 0);
+    auto wrap = [](long long v, long long m) { return (int)(((v % m) + m) % m); };
+    for (size_t i = 0; i < d->bnd_x.size(); ++i) {
+        const int x = d->bnd_x[i], y = d->bnd_y[i];
+        const int s0 = (int)((long long)x * ns / nx), g0 = y / H;
+        for (int ds = -1; ds <= 1; ++ds) {
+            const int s = wrap(s0 + ds, ns);
+            const int x0 = (int)((long long)s * nx / ns);
+            if (wrap((long long)x - (x0 - kF2Halo), nx) >= kF2Lanes) continue;
+            for (int dg = -1; dg <= 1; ++dg) {
+                const int g = wrap(g0 + dg, ng);
+                const int y0 = g * H, h = std::min(H, ny - y0);
+                if (wrap((long long)y - (y0 - 1), ny) >= h + 2) continue;
+                w[(size_t)g * ns + s] += 1;
+            }
+        }
+    }
+    std::vector<int> nat((size_t)n), pos((size_t)n), order((size_t)n);
+    for (int b = 0; b < n; ++b) {
+        nat[b] = xcd_tile(b, n);
+        pos[b] = b;
+    }
+    std::stable_sort(pos.begin(), pos.end(),
+                     [&](int a, int b) { return w[nat[a]] > w[nat[b]]; });
+    for (int b = 0; b < n; ++b) order[b] = nat[pos[b]];
+    if (hipMemcpyAsync(d->tile_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice,
+                       d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return LBM_EDEVICE;
+    return LBM_OK;
+}
+
 // -------------------------------------------------------------- creation
 struct LinkRec {
     int node;  // x_b index in y*nx + x
@@ -632,6 +677,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
         // the two-step pass keeps (first link slot + 1) << 8 | flags in an int
         if (lnode.size() + 1 >= (size_t(1) << 23)) d->fusable = false;
         node_link[pidx(x, y)] = (int)lnode.size() + 1;
+        d->bnd_x.push_back(x);
+        d->bnd_y.push_back(y);
         if (d->save_f) flags[pidx(x, y)] |= FL_SAVE_F;
         ++nb;
         for (long long k = k0; k < k1; ++k) {
@@ -776,6 +823,8 @@ int validate_and_build(const lbm_desc* s, lbm_domain* d) {
     if (d->fusable) {
         if ((rc = dev_alloc(d, (void**)&d->partial2, (size_t)d->partial_cap * 8))) return rc;
         if ((rc = upload(d, &d->node_link, node_link))) return rc;
+        if ((rc = dev_alloc(d, (void**)&d->tile_order, (size_t)d->partial_cap * 4))) return rc;
+        if ((rc = order_tiles(d))) return rc;
         // the replay of the intermediate step (moments and wall force after
         // a two-step pass), held from the start so that reading them never
         // allocates
@@ -1228,6 +1277,8 @@ int lbm_set_steps_per_pass(lbm_domain* d, int32_t steps, int32_t tile_h) {
         d->tile_h2 = th;
         d->nsegs2 = ng;
         d->nblocks2 = d->nstrips2 * ng;
+        const int rc = order_tiles(d);
+        if (rc) return rc;
     }
     drop_graphs(d);
     d->fused = steps;
