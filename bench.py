@@ -542,12 +542,16 @@ def two_step_leg(steps, warmup, stream, prof_steps):
     from lbm_inputs import configs as cfg
     from paper_1908_09235_amd import lbm
 
+    # (name, problem, storage forms, rows per two-step tile: 0 for the
+    # library's default; the droplet's walls run along whole strips, where
+    # shorter tiles pay)
     cases = [("shear_wave_2048x2048_bgk", lambda: cfg.shear_wave(2048, nx=2048, collision="bgk"),
-              ("f32_arith32", "f32")),
-             ("droplet_cylinder_2048x2048_mrt_mls_B", cfg.cfg2a, ("f32",)),
-             ("cylinders96_8192x4096_bgk_mls_B", cfg.many_cylinders, ("f32_arith32", "f32dev"))]
+              ("f32_arith32", "f32"), 0),
+             ("droplet_cylinder_2048x2048_mrt_mls_B", cfg.cfg2a, ("f32",), 8),
+             ("droplet_cylinder_2048x2048_mrt_mls_B", cfg.cfg2a, ("f32_arith32",), 5),
+             ("cylinders96_8192x4096_bgk_mls_B", cfg.many_cylinders, ("f32_arith32", "f32dev"), 0)]
     out = {}
-    for name, make, storages in cases:
+    for name, make, storages, tile_h in cases:
         p = make()
         fluid = int((~p.solid.astype(bool)).sum())
         for st in storages:
@@ -555,7 +559,8 @@ def two_step_leg(steps, warmup, stream, prof_steps):
             for spp in (1, 2):
                 d = lbm.Domain(p, storage=st, stream=stream, history_capacity=1 << 12)
                 if spp == 2:
-                    lbm.lbm_set_steps_per_pass(d.h, 2, 0)
+                    lbm.lbm_set_steps_per_pass(d.h, 2, tile_h)
+                    th_used = lbm.lbm_get_steps_per_pass(d.h)[1]
                 d.step(warmup)  # also captures the step graphs
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -579,7 +584,8 @@ def two_step_leg(steps, warmup, stream, prof_steps):
                     "algorithmic_bytes_per_launch": alg,
                     "effective_gbs": gbs and round(gbs, 1),
                     "frac": gbs and round(gbs / PEAK_HBM_GBS, 4)}
-            out[f"{name}:{st}"] = rec
+            rec["two_step_tile_h"] = th_used
+            out[f"{name}:{st}" + (f":tile_h{tile_h}" if tile_h else "")] = rec
     return out
 
 

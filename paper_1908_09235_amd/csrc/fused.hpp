@@ -74,8 +74,12 @@ struct Pull2 {
     S f[9];
 };
 
+// (at least three wavefronts per SIMD: 168 registers; the Carnahan-Starling
+// variants fit without spilling in FP32 storage, the FP16 ones spill 12
+// bytes per lane and still run faster than at two wavefronts)
 template <typename S, typename R, int EOS, int DEV>
-__global__ __launch_bounds__(kF2Lanes) void k_main2(Main2Args<S> a, Phys<R> ph) {
+__global__ __launch_bounds__(kF2Lanes) __attribute__((amdgpu_waves_per_eu(3))) void k_main2(
+    Main2Args<S> a, Phys<R> ph) {
     static_assert(DEV == 0 || DEV == 1, "per-node references are not fused");
     // ring rows of f*(t + 1), of the moments of t + 1 and of the flags: the
     // rows m - 1 .. m + 1 around the row m being pulled, the newest being
