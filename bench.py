@@ -536,7 +536,8 @@ def two_step_leg(steps, warmup, stream, prof_steps):
     mean duration of the main launch over a separate pass of `prof_steps`
     steps (each launch records its own start and end).  The effective rate
     counts the algorithmic bytes of the steps one launch advances, 18
-    populations per fluid node per step, against the HBM peak."""
+    populations per fluid node per step, against the HBM peak.  `tuned` is
+    the setting lbm_tune_steps_per_pass picks on a fresh domain."""
     import torch
 
     from lbm_inputs import configs as cfg
@@ -585,6 +586,9 @@ def two_step_leg(steps, warmup, stream, prof_steps):
                     "effective_gbs": gbs and round(gbs, 1),
                     "frac": gbs and round(gbs / PEAK_HBM_GBS, 4)}
             rec["two_step_tile_h"] = th_used
+            # what the library's own tuner picks for this case
+            with lbm.Domain(p, storage=st, stream=stream, history_capacity=1 << 12) as d:
+                rec["tuned"] = d.tune_steps_per_pass(max(50, steps // 20))
             out[f"{name}:{st}" + (f":tile_h{tile_h}" if tile_h else "")] = rec
     return out
 

@@ -275,6 +275,19 @@ int lbm_negative_rest(lbm_domain *d, int64_t *count);
  * the last step come from a replay of the intermediate step, in buffers
  * held since creation. */
 int lbm_set_steps_per_pass(lbm_domain *d, int32_t steps, int32_t tile_h);
+
+/* Autotuner for lbm_set_steps_per_pass: runs steps_per_trial >= 2 steps
+ * untimed (they capture the step graphs), then steps_per_trial steps timed
+ * on the domain's stream, under each setting -- one step per pass, and
+ * where two are available two per pass with tiles of 4, 6, 8, 12, 16 and
+ * 24 rows -- keeps the fastest and reports in out: steps per pass, rows
+ * per tile (of the single-step kernel when one step per pass wins),
+ * microseconds per step.  The steps count as steps of the domain (2 x
+ * steps_per_trial per setting); every setting gives the same results bit
+ * for bit.  Waits for the domain's stream.  LBM_EINVAL for NULL arguments
+ * or steps_per_trial < 2; LBM_EUNSTABLE (out filled) if a step was
+ * unstable. */
+int lbm_tune_steps_per_pass(lbm_domain *d, int64_t steps_per_trial, int32_t out[3]);
 int lbm_get_steps_per_pass(lbm_domain *d, int32_t *steps, int32_t *tile_h);
 
 /* Scheme B (Eq. 22) and Bao et al. (Eq. 23) divide by a sum over the

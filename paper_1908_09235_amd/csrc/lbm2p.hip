@@ -1292,6 +1292,54 @@ int lbm_get_steps_per_pass(lbm_domain* d, int32_t* steps, int32_t* tile_h) {
     return LBM_OK;
 }
 
+int lbm_tune_steps_per_pass(lbm_domain* d, int64_t steps_per_trial, int32_t out[3]) {
+    if (!d || !out || steps_per_trial < 2) return LBM_EINVAL;
+    struct Cand {
+        int steps, tile_h;
+    };
+    std::vector<Cand> cands{{1, 0}};
+    if (d->fusable)
+        for (int th : {4, 6, 8, 12, 16, 24})
+            if ((long long)d->nstrips2 * ((d->ny + th - 1) / th) <= d->partial_cap)
+                cands.push_back({2, th});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return LBM_EDEVICE;
+    }
+    // whole runs are timed, so the steps replay their graphs as lbm_step does
+    const int prof = d->prof;
+    d->prof = 0;
+    int rc = LBM_OK;
+    float best = 0.0f;
+    Cand pick = cands[0];
+    for (const Cand& c : cands) {
+        if ((rc = lbm_set_steps_per_pass(d, c.steps, c.tile_h))) break;
+        if ((rc = run_steps(d, steps_per_trial))) break;  // also captures the graphs
+        float ms = 0.0f;
+        if (hipEventRecord(e0, d->stream) != hipSuccess ||
+            (rc = run_steps(d, steps_per_trial)) != LBM_OK ||
+            hipEventRecord(e1, d->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            if (!rc) rc = LBM_EDEVICE;
+            break;
+        }
+        if (&c == &cands[0] || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    d->prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = lbm_set_steps_per_pass(d, pick.steps, pick.tile_h))) return rc;
+    out[0] = pick.steps;
+    out[1] = pick.steps == 2 ? d->tile_h2 : d->tile_h;
+    out[2] = (int32_t)std::lround(1000.0 * best / (double)steps_per_trial);
+    return check_unstable(d);
+}
+
 int lbm_degenerate_b(lbm_domain* d, int64_t* count) {
     if (!d || !count) return LBM_EINVAL;
     unsigned long long n = 0;

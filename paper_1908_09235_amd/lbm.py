@@ -88,6 +88,7 @@ EXPORTS = {
     "lbm_info": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_set_steps_per_pass": (C.c_int, [_H, C.c_int32, C.c_int32]),
     "lbm_get_steps_per_pass": (C.c_int, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbm_tune_steps_per_pass": (C.c_int, [_H, C.c_int64, C.POINTER(C.c_int32)]),
     "lbm_negative_rest": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_degenerate_b": (C.c_int, [_H, C.POINTER(C.c_int64)]),
     "lbm_destroy": (None, [_H]),
@@ -326,6 +327,14 @@ def lbm_get_steps_per_pass(h):
     return s.value, t.value
 
 
+def lbm_tune_steps_per_pass(h, steps_per_trial):
+    """Times one and two steps per pass (tiles of 4..24 rows) on real steps
+    and keeps the fastest; returns {steps_per_pass, tile_h, us_per_step}."""
+    out = (C.c_int32 * 3)()
+    _check(lib().lbm_tune_steps_per_pass(h, int(steps_per_trial), out), "lbm_tune_steps_per_pass")
+    return {"steps_per_pass": out[0], "tile_h": out[1], "us_per_step": out[2]}
+
+
 def lbm_status_string(code):
     return lib().lbm_status_string(code).decode()
 
@@ -364,6 +373,9 @@ class Domain:
 
     def degenerate_b(self):
         return lbm_degenerate_b(self.h)
+
+    def tune_steps_per_pass(self, steps_per_trial=100):
+        return lbm_tune_steps_per_pass(self.h, steps_per_trial)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

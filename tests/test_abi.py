@@ -42,6 +42,8 @@ def test_null_arguments_are_rejected(L):
     assert lib.lbm_moments(None, None, None, None) == L.LBM_EINVAL
     assert lib.lbm_wall_force(None, None) == L.LBM_EINVAL
     assert lib.lbm_negative_rest(None, None) == L.LBM_EINVAL
+    out3 = (ctypes.c_int32 * 3)()
+    assert lib.lbm_tune_steps_per_pass(None, 4, out3) == L.LBM_EINVAL
     n = ctypes.c_size_t()
     assert lib.lbm_get_state(None, None, ctypes.byref(n)) == L.LBM_EINVAL
     lib.lbm_destroy(None)

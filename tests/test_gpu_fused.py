@@ -147,3 +147,24 @@ def test_two_steps_refused_where_not_available(L):
             assert L.lbm_get_steps_per_pass(d.h)[0] == 1
             assert L.lib().lbm_set_steps_per_pass(d.h, 2, 0) == L.LBM_EINVAL
             assert L.lbm_get_steps_per_pass(d.h)[0] == 1
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32_arith32", "f64"])
+def test_tuner_keeps_results(L, storage):
+    """lbm_tune_steps_per_pass times every setting on real steps and keeps
+    the fastest; the steps it runs are steps of the domain and give the
+    same fields as single steps (FP64 storage has only one setting)."""
+    p = cfg.cfg1("mls", "B")
+    with L.Domain(p, storage=storage, history_capacity=4096) as a, \
+            L.Domain(p, storage=storage, history_capacity=4096) as b:
+        best = a.tune_steps_per_pass(4)
+        say(f"[gpu] tuned {storage}: {best}")
+        assert best["steps_per_pass"] in (1, 2) and best["tile_h"] > 0 and best["us_per_step"] > 0
+        if storage == "f64":
+            assert best["steps_per_pass"] == 1
+        assert L.lbm_get_steps_per_pass(a.h) == (best["steps_per_pass"], best["tile_h"])
+        a.step(7)
+        b.step(a.t)
+        _same(a, b, f"tuned {storage}")
+        with pytest.raises(L.LbmError):
+            L.lbm_tune_steps_per_pass(a.h, 1)
