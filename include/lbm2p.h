@@ -286,7 +286,7 @@ int lbm_set_steps_per_pass(lbm_domain *d, int32_t steps, int32_t tile_h);
  * steps_per_trial per setting); every setting gives the same results bit
  * for bit.  Waits for the domain's stream.  LBM_EINVAL for NULL arguments
  * or steps_per_trial < 2; LBM_EUNSTABLE (out filled) if a step was
- * unstable. */
+ * unstable; on a device error the caller's setting is restored. */
 int lbm_tune_steps_per_pass(lbm_domain *d, int64_t steps_per_trial, int32_t out[3]);
 int lbm_get_steps_per_pass(lbm_domain *d, int32_t *steps, int32_t *tile_h);
 

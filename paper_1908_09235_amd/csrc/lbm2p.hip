@@ -1308,7 +1308,7 @@ int lbm_tune_steps_per_pass(lbm_domain* d, int64_t steps_per_trial, int32_t out[
         return LBM_EDEVICE;
     }
     // whole runs are timed, so the steps replay their graphs as lbm_step does
-    const int prof = d->prof;
+    const int prof = d->prof, steps0 = d->fused, tile0 = d->tile_h2;
     d->prof = 0;
     int rc = LBM_OK;
     float best = 0.0f;
@@ -1332,7 +1332,11 @@ int lbm_tune_steps_per_pass(lbm_domain* d, int64_t steps_per_trial, int32_t out[
     d->prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc) return rc;
+    if (rc) {
+        // the caller's setting again (it was valid when set)
+        (void)lbm_set_steps_per_pass(d, steps0, steps0 == 2 ? tile0 : 0);
+        return rc;
+    }
     if ((rc = lbm_set_steps_per_pass(d, pick.steps, pick.tile_h))) return rc;
     out[0] = pick.steps;
     out[1] = pick.steps == 2 ? d->tile_h2 : d->tile_h;
